@@ -1,0 +1,346 @@
+/* Plain CPU oracle for batched LU with partial pivoting and for the per-point
+ * Newton constitutive update — TEST INFRASTRUCTURE ONLY (see lupp_oracle.h).
+ *
+ * Every routine is the textbook definition written out with plain loops, in
+ * the order the paper describes it, so that it can be checked against the
+ * paper by eye.  Build: gcc -O2 -ffp-contract=off (no fast-math).
+ */
+#include "lupp_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* LU with partial pivoting (Section 2.2).                                   */
+/* Right-looking Gaussian elimination: at step k the pivot is the candidate  */
+/* of largest magnitude in column k (lowest row index on ties), rows k and p */
+/* are exchanged across all columns, the multipliers l_ik = a_ik / a_kk are  */
+/* stored below the diagonal, and the trailing submatrix (Schur complement)  */
+/* receives a_ij <- a_ij - l_ik * u_kj.                                      */
+/* ------------------------------------------------------------------------ */
+int oracle_getrf(int n, double *a, int lda, int32_t *ipiv, double *gap)
+{
+    int info = 0;
+    double g = 1.0;
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = fabs(a[k + (int64_t)k * lda]);
+        for (int i = k + 1; i < n; ++i) {
+            double v = fabs(a[i + (int64_t)k * lda]);
+            if (v > best) {
+                best = v;
+                p = i;
+            }
+        }
+        if (gap != NULL && k + 1 < n) {
+            double second = -1.0;
+            for (int i = k; i < n; ++i) {
+                if (i == p) continue;
+                double v = fabs(a[i + (int64_t)k * lda]);
+                if (v > second) second = v;
+            }
+            double gk = best > 0.0 ? (best - second) / best : 0.0;
+            if (gk < g) g = gk;
+        }
+        ipiv[k] = p + 1;
+        if (a[p + (int64_t)k * lda] == 0.0) {
+            if (info == 0) info = k + 1;
+            continue;
+        }
+        if (p != k) {
+            for (int j = 0; j < n; ++j) {
+                double t = a[k + (int64_t)j * lda];
+                a[k + (int64_t)j * lda] = a[p + (int64_t)j * lda];
+                a[p + (int64_t)j * lda] = t;
+            }
+        }
+        for (int i = k + 1; i < n; ++i)
+            a[i + (int64_t)k * lda] = a[i + (int64_t)k * lda] / a[k + (int64_t)k * lda];
+        for (int j = k + 1; j < n; ++j)
+            for (int i = k + 1; i < n; ++i)
+                a[i + (int64_t)j * lda] =
+                    a[i + (int64_t)j * lda] - a[i + (int64_t)k * lda] * a[k + (int64_t)j * lda];
+    }
+    if (gap != NULL) *gap = g;
+    return info;
+}
+
+/* Triangular solves (Section 2.2): apply the interchanges to b, then L y = P b
+ * (unit lower, column by column, ascending), then U x = y (column by column,
+ * descending: divide by the diagonal, then eliminate the column above it). */
+void oracle_getrs(int n, const double *lu, int lda, const int32_t *ipiv, double *b)
+{
+    for (int k = 0; k < n; ++k) {
+        int p = ipiv[k] - 1;
+        if (p != k) {
+            double t = b[k];
+            b[k] = b[p];
+            b[p] = t;
+        }
+    }
+    for (int j = 0; j < n; ++j)
+        for (int i = j + 1; i < n; ++i)
+            b[i] = b[i] - lu[i + (int64_t)j * lda] * b[j];
+    for (int j = n - 1; j >= 0; --j) {
+        b[j] = b[j] / lu[j + (int64_t)j * lda];
+        for (int i = 0; i < j; ++i)
+            b[i] = b[i] - lu[i + (int64_t)j * lda] * b[j];
+    }
+}
+
+int oracle_gesv(int n, double *a, int lda, double *b, int32_t *ipiv, double *gap)
+{
+    int info = oracle_getrf(n, a, lda, ipiv, gap);
+    if (info == 0) oracle_getrs(n, a, lda, ipiv, b);
+    return info;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Batch drivers: one system per task, static chunks over POSIX threads.     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    void (*body)(void *ctx, int64_t lo, int64_t hi);
+    void *ctx;
+    int64_t lo, hi;
+} oracle_task;
+
+static void *oracle_task_run(void *p)
+{
+    oracle_task *t = (oracle_task *)p;
+    t->body(t->ctx, t->lo, t->hi);
+    return NULL;
+}
+
+static void oracle_parallel_for(int64_t count, int nthreads,
+                                void (*body)(void *, int64_t, int64_t), void *ctx)
+{
+    if (nthreads <= 1 || count < 2) {
+        body(ctx, 0, count);
+        return;
+    }
+    if (nthreads > 256) nthreads = 256;
+    if (nthreads > count) nthreads = (int)count;
+    pthread_t th[256];
+    oracle_task tk[256];
+    int started[256];
+    int64_t per = (count + nthreads - 1) / nthreads;
+    for (int t = 0; t < nthreads; ++t) {
+        tk[t].body = body;
+        tk[t].ctx = ctx;
+        tk[t].lo = t * per < count ? t * per : count;
+        tk[t].hi = (t + 1) * per < count ? (t + 1) * per : count;
+        started[t] = pthread_create(&th[t], NULL, oracle_task_run, &tk[t]) == 0;
+        if (!started[t]) oracle_task_run(&tk[t]);
+    }
+    for (int t = 0; t < nthreads; ++t)
+        if (started[t]) pthread_join(th[t], NULL);
+}
+
+typedef struct {
+    int n, lda;
+    int64_t strideA, strideB;
+    double *a, *b, *gap;
+    int32_t *ipiv, *info;
+} batch_ctx;
+
+static void batch_body(void *p, int64_t lo, int64_t hi)
+{
+    batch_ctx *c = (batch_ctx *)p;
+    for (int64_t s = lo; s < hi; ++s) {
+        double g;
+        c->info[s] = oracle_gesv(c->n, c->a + s * c->strideA, c->lda, c->b + s * c->strideB,
+                                 c->ipiv + s * c->n, c->gap ? &g : NULL);
+        if (c->gap) c->gap[s] = g;
+    }
+}
+
+void oracle_gesv_batch(int n, int64_t batch, double *a, int lda, int64_t strideA,
+                       double *b, int64_t strideB, int32_t *ipiv, int32_t *info,
+                       double *gap, int nthreads)
+{
+    batch_ctx c = {n, lda, strideA, strideB, a, b, gap, ipiv, info};
+    oracle_parallel_for(batch, nthreads, batch_body, &c);
+}
+
+typedef struct {
+    const int32_t *n;
+    const int64_t *offA, *offB;
+    double *a, *b;
+    int32_t *ipiv, *info;
+} ragged_ctx;
+
+static void ragged_body(void *p, int64_t lo, int64_t hi)
+{
+    ragged_ctx *c = (ragged_ctx *)p;
+    for (int64_t s = lo; s < hi; ++s)
+        c->info[s] = oracle_gesv(c->n[s], c->a + c->offA[s], c->n[s], c->b + c->offB[s],
+                                 c->ipiv + c->offB[s], NULL);
+}
+
+void oracle_gesv_ragged(int64_t batch, const int32_t *n, const int64_t *offA,
+                        const int64_t *offB, double *a, double *b, int32_t *ipiv,
+                        int32_t *info, int nthreads)
+{
+    ragged_ctx c = {n, offA, offB, a, b, ipiv, info};
+    oracle_parallel_for(batch, nthreads, ragged_body, &c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Constitutive laws, Kelvin-Mandel notation, backward Euler.                */
+/*                                                                          */
+/* eel = eel_t + d_eel, sig = lambda tr(eel) 1 + 2 mu eel, s = K sig with    */
+/* K = I - 1/3 1 1^T.  Norton: xi = s; with Armstrong-Frederick:             */
+/* alpha = alpha_t + d_alpha, X = 2/3 C alpha, xi = s - X.                   */
+/* seq = sqrt(3/2 xi.xi), N = 3/2 xi / seq (N = 0 when seq = 0).             */
+/* Residuals: F_e = d_eel + dp N - deps;  F_p = dp - dt A seq^m;             */
+/*            F_a = d_alpha - dp N + D dp alpha.                            */
+/* The Jacobian is the exact derivative of these residuals.                  */
+/* ------------------------------------------------------------------------ */
+void oracle_law_eval(const oracle_law *law, const double *deps, const double *state_t,
+                     const double *y, double *F, double *J, double *sig)
+{
+    const int nunk = law->kind;
+    const int af = (law->kind == 13);
+    const double lam = law->E * law->nu / ((1.0 + law->nu) * (1.0 - 2.0 * law->nu));
+    const double mu = law->E / (2.0 * (1.0 + law->nu));
+
+    double eel[6], s[6], xi[6], alpha[6], N[6];
+    for (int i = 0; i < 6; ++i) eel[i] = state_t[i] + y[i];
+    double tr = eel[0] + eel[1] + eel[2];
+    for (int i = 0; i < 6; ++i) sig[i] = 2.0 * mu * eel[i] + (i < 3 ? lam * tr : 0.0);
+    double trs = sig[0] + sig[1] + sig[2];
+    for (int i = 0; i < 6; ++i) s[i] = sig[i] - (i < 3 ? trs / 3.0 : 0.0);
+    for (int i = 0; i < 6; ++i) {
+        alpha[i] = af ? state_t[7 + i] + y[7 + i] : 0.0;
+        xi[i] = s[i] - (af ? 2.0 / 3.0 * law->C * alpha[i] : 0.0);
+    }
+    double xx = 0.0;
+    for (int i = 0; i < 6; ++i) xx += xi[i] * xi[i];
+    double seq = sqrt(1.5 * xx);
+    for (int i = 0; i < 6; ++i) N[i] = seq > 0.0 ? 1.5 * xi[i] / seq : 0.0;
+
+    const double dp = y[6];
+    for (int i = 0; i < 6; ++i) F[i] = y[i] + dp * N[i] - deps[i];
+    F[6] = dp - law->dt * law->A * pow(seq, law->m);
+    if (af)
+        for (int i = 0; i < 6; ++i) F[7 + i] = y[7 + i] - dp * N[i] + law->D * dp * alpha[i];
+
+    if (J == NULL) return;
+    for (int c = 0; c < nunk * nunk; ++c) J[c] = 0.0;
+#define JAC(r, c) J[(r) + (c) * nunk]
+    /* dN/dxi = (3/2 I - N N^T) / seq, the deviatoric projector K, and
+     * (dN/dxi) K which is dN/d(d_eel) divided by 2 mu. */
+    double Hp[6][6], Km[6][6], HK[6][6], KN[6];
+    for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+            Hp[a][b] = seq > 0.0 ? (1.5 * (a == b ? 1.0 : 0.0) - N[a] * N[b]) / seq : 0.0;
+            Km[a][b] = (a == b ? 1.0 : 0.0) - (a < 3 && b < 3 ? 1.0 / 3.0 : 0.0);
+        }
+    for (int a = 0; a < 6; ++a) {
+        KN[a] = 0.0;
+        for (int b = 0; b < 6; ++b) KN[a] += Km[a][b] * N[b];
+        for (int b = 0; b < 6; ++b) {
+            HK[a][b] = 0.0;
+            for (int c = 0; c < 6; ++c) HK[a][b] += Hp[a][c] * Km[c][b];
+        }
+    }
+    /* d(dt A seq^m)/dseq */
+    const double gdot = seq > 0.0 ? law->dt * law->A * law->m * pow(seq, law->m - 1.0) : 0.0;
+    for (int a = 0; a < 6; ++a) {
+        for (int b = 0; b < 6; ++b) JAC(a, b) = (a == b ? 1.0 : 0.0) + dp * 2.0 * mu * HK[a][b];
+        JAC(a, 6) = N[a];
+        JAC(6, a) = -gdot * 2.0 * mu * KN[a];
+    }
+    JAC(6, 6) = 1.0;
+    if (af) {
+        const double c23 = 2.0 / 3.0 * law->C;
+        for (int a = 0; a < 6; ++a) {
+            for (int b = 0; b < 6; ++b) {
+                JAC(a, 7 + b) = -c23 * dp * Hp[a][b];
+                JAC(7 + a, b) = -dp * 2.0 * mu * HK[a][b];
+                JAC(7 + a, 7 + b) = (1.0 + law->D * dp) * (a == b ? 1.0 : 0.0) + c23 * dp * Hp[a][b];
+            }
+            JAC(6, 7 + a) = c23 * gdot * N[a];
+            JAC(7 + a, 6) = -N[a] + law->D * alpha[a];
+        }
+    }
+#undef JAC
+}
+
+/* Newton-Raphson for one point (Section 2.1, Algorithm 2): start from zero
+ * increments; at each iterate evaluate F; stop on a non-finite residual, on
+ * ||F||_inf < tol, or after maxit linear solves; otherwise factor J with
+ * partial pivoting, solve J dx = -F and update x += dx. */
+static void oracle_newton_point(const oracle_law *law, const double *deps, double *state,
+                                double *sig, int32_t *iters, int32_t *status, double *resid,
+                                double tol, int maxit)
+{
+    const int nunk = law->kind;
+    double y[13], F[13], J[169], dx[13];
+    int32_t piv[13];
+    memset(y, 0, sizeof(y));
+    int st = 1, k = 0;
+    double nrm = 0.0;
+    for (k = 0;; ++k) {
+        oracle_law_eval(law, deps, state, y, F, J, sig);
+        int finite = 1;
+        nrm = 0.0;
+        for (int i = 0; i < nunk; ++i) {
+            if (!isfinite(F[i])) finite = 0;
+            else if (fabs(F[i]) > nrm) nrm = fabs(F[i]);
+        }
+        if (!finite) {
+            st = 3;
+            nrm = NAN;
+            break;
+        }
+        if (nrm < tol) {
+            st = 0;
+            break;
+        }
+        if (k == maxit) {
+            st = 1;
+            break;
+        }
+        for (int i = 0; i < nunk; ++i) dx[i] = -F[i];
+        if (oracle_gesv(nunk, J, nunk, dx, piv, NULL) != 0) {
+            st = 2;
+            break;
+        }
+        for (int i = 0; i < nunk; ++i) y[i] = y[i] + dx[i];
+    }
+    *iters = k;
+    *status = st;
+    *resid = nrm;
+    if (st == 0)
+        for (int i = 0; i < nunk; ++i) state[i] = state[i] + y[i];
+}
+
+typedef struct {
+    const oracle_law *law;
+    const double *deps;
+    double *state, *sig, *resid;
+    int32_t *iters, *status;
+    double tol;
+    int maxit;
+} newton_ctx;
+
+static void newton_body(void *p, int64_t lo, int64_t hi)
+{
+    newton_ctx *c = (newton_ctx *)p;
+    const int nunk = c->law->kind;
+    for (int64_t s = lo; s < hi; ++s)
+        oracle_newton_point(c->law, c->deps + 6 * s, c->state + nunk * s, c->sig + 6 * s,
+                            c->iters + s, c->status + s, c->resid + s, c->tol, c->maxit);
+}
+
+void oracle_constitutive_update(const oracle_law *law, int64_t count, const double *deps,
+                                double *state, double *sig, int32_t *iters,
+                                int32_t *status, double *resid, double tol, int maxit,
+                                int nthreads)
+{
+    newton_ctx c = {law, deps, state, sig, resid, iters, status, tol, maxit};
+    oracle_parallel_for(count, nthreads, newton_body, &c);
+}
