@@ -1,0 +1,181 @@
+/* lupp — batched LU with partial pivoting for millions of tiny (n <= 32)
+ * double-precision systems, and a fused per-point Newton constitutive update,
+ * on AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The operations follow the paper "Accelerating the Solving of Many Tiny
+ * General Linear Systems on GPUs: Application to Constitutive Laws":
+ *   - PA = LU by Gaussian elimination with partial pivoting, then L y = P b and
+ *     U x = y (Section 2.2);
+ *   - host-launched batched solves over device arrays of independent systems
+ *     (Section 3.1, the getrf/getrs/gesv roles);
+ *   - a device-callable solve used inside a per-point Newton loop, the whole
+ *     loop in one kernel (Section 2.1, equations 1-3; Section 3.3; Algorithm 2).
+ *
+ * Conventions for every entry point:
+ *   - Array pointers are DEVICE pointers owned by the caller. The library never
+ *     frees them and keeps no reference after the work it enqueued completes.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream): results are valid once that stream's work completes.
+ *   - Return value: 0 on success; -k if the k-th argument is invalid (nothing
+ *     is enqueued, nothing is printed); LUPP_E_UNSUPPORTED for a valid request
+ *     this build cannot serve; LUPP_E_HIP_BASE - e for a HIP runtime error e.
+ *     No C++ exception crosses the ABI.
+ *   - Numerics (strict mode): IEEE binary64, no FMA contraction, true
+ *     divisions. Results are bitwise identical to the textbook algorithm's
+ *     whatever kernel variant, layout or batch composition serves a call.
+ */
+#ifndef LUPP_H
+#define LUPP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LUPP_E_UNSUPPORTED (-900)
+#define LUPP_E_NOMEM (-901)
+#define LUPP_E_HIP_BASE (-1000)
+
+/* Matrix layouts.
+ * LUPP_AOS: system s, element (i, j) at A[s*strideA + i + j*lda] (column-major
+ *           per system); b[s*strideB + i]; ipiv[s*n + k].
+ * LUPP_SOA: interleaved: A[(i + j*lda)*ldbatch + s]; b[i*strideB + s];
+ *           ipiv[k*ldbatch + s]. Consecutive systems are adjacent in memory,
+ *           so lane s of a wave reads consecutive doubles. */
+#define LUPP_AOS 0
+#define LUPP_SOA 1
+
+/* Flags. LUPP_KEEP_A: do not write the factors back (A is left unchanged). */
+#define LUPP_KEEP_A 1u
+
+/* Kernel variants (for lupp_force_variant and lupp_variant_info). */
+#define LUPP_VARIANT_AUTO 0
+#define LUPP_VARIANT_THREAD 1 /* one lane per system, registers only      */
+#define LUPP_VARIANT_LANES 2  /* `lanes` lanes per system (segment of a wave64) */
+
+typedef struct lupp_ctx lupp_ctx;
+
+/* Create a context bound to HIP device `device` (its current state is not
+ * changed). The context owns the per-size dispatch table and the library's
+ * device workspace. One context may be used from one host thread at a time.
+ * Returns 0 or an error; *ctx is NULL on error. */
+int lupp_create(lupp_ctx **ctx, int device);
+
+/* Release a context (waits for nothing: the caller synchronises its streams
+ * first). NULL is accepted. */
+void lupp_destroy(lupp_ctx *ctx);
+
+/* Batched dgesv (Section 2.2; Section 3.1): for each of `batch` independent
+ * n x n systems, factor PA = LU with partial pivoting and, where the
+ * factorisation has no zero pivot, overwrite b with x = A^-1 b.
+ *   n       : 1..32.
+ *   batch   : >= 0 (0 is a no-op).
+ *   layout  : LUPP_AOS or LUPP_SOA.
+ *   A       : matrices; on return the LAPACK-ordered factors L\U (unit lower L
+ *             below the diagonal, U on and above), unless LUPP_KEEP_A.
+ *   lda     : >= n.
+ *   strideA : AoS: distance between systems, >= lda*n.
+ *             SoA: ldbatch, the distance between consecutive elements of one
+ *             system, >= batch.
+ *   b       : right-hand sides, overwritten by the solutions where info == 0
+ *             and left unchanged where info > 0.
+ *   strideB : AoS: >= n; SoA: >= batch.
+ *   ipiv    : int32 LAPACK interchange sequence: ipiv[k] = r (1-based) means
+ *             rows k+1 and r were exchanged at step k; r >= k+1.
+ *   info    : int32 per system: 0, or k+1 for the first step k whose pivot
+ *             is exactly zero (the factorisation still completes).
+ *   flags   : 0 or LUPP_KEEP_A.
+ * Inputs containing NaN or Inf produce unspecified factors and info. */
+int lupp_batched_solve(lupp_ctx *ctx, int n, int64_t batch, int layout, double *A, int64_t lda,
+                       int64_t strideA, double *b, int64_t strideB, int32_t *ipiv,
+                       int32_t *info, unsigned flags, void *stream);
+
+/* Validate the arguments of lupp_batched_solve (numbered as in that call,
+ * ctx being argument 1) without enqueuing anything: 0 or -k. Host-only; it
+ * needs no device. */
+int lupp_check_solve_args(int n, int64_t batch, int layout, const double *A, int64_t lda,
+                          int64_t strideA, const double *b, int64_t strideB, const int32_t *ipiv,
+                          const int32_t *info, unsigned flags);
+
+/* Mixed sizes in one launch (Section 4.1: size-aware dispatch): system s has
+ * size n[s] in 1..32, its matrix column-major at A + offA[s] with lda = n[s],
+ * its right-hand side at b + offB[s] and its pivots at ipiv + offB[s].
+ * Systems must not overlap. n, offA, offB are device arrays of `batch`
+ * entries. The library groups systems by size on the device (workspace owned
+ * by the context) and serves every group from one persistent kernel launch. */
+int lupp_batched_solve_ragged(lupp_ctx *ctx, int64_t batch, const int32_t *n,
+                              const int64_t *offA, const int64_t *offB, double *A, double *b,
+                              int32_t *ipiv, int32_t *info, unsigned flags, void *stream);
+
+/* Restrict later lupp_batched_solve calls on this context to one variant
+ * (LUPP_VARIANT_AUTO restores the size-aware dispatch table). lanes is the
+ * segment width for LUPP_VARIANT_LANES (2, 4, 8, 16 or 32), wpb the number of
+ * wave64s per workgroup (1, 2 or 4; 0 = default). Returns LUPP_E_UNSUPPORTED
+ * if a later call's n cannot be served by the forced variant. */
+int lupp_force_variant(lupp_ctx *ctx, int variant, int lanes, int wpb);
+
+/* Set the dispatch-table entry used for size n and layout: the autotuner
+ * writes its choice through this call. */
+int lupp_set_dispatch(lupp_ctx *ctx, int n, int layout, int variant, int lanes, int wpb);
+int lupp_get_dispatch(lupp_ctx *ctx, int n, int layout, int *variant, int *lanes, int *wpb);
+
+/* Compile-time resources of one kernel variant: VGPRs, AGPRs and SGPRs per
+ * lane, private (scratch) bytes per lane, and LDS bytes per workgroup.
+ * Returns LUPP_E_UNSUPPORTED if the variant does not exist. */
+typedef struct {
+    int vgprs, agprs, sgprs, scratch_bytes, lds_bytes, max_threads;
+} lupp_kernel_info;
+int lupp_variant_info(int n, int layout, int variant, int lanes, int keep_a,
+                      lupp_kernel_info *out);
+
+/* ---------------------------------------------------------------------------
+ * Implicit constitutive update with a fused Newton loop (Section 2.1;
+ * Section 3.3; Algorithm 2): one kernel in which every integration point runs
+ * its own Newton iterations, assembling the residual F and Jacobian J of the
+ * law, solving J dx = -F with the device-callable LU, and updating x += dx,
+ * until ||F||_inf < tol.
+ *
+ * Laws (Kelvin-Mandel vectors, backward Euler, unknowns x):
+ *   LUPP_LAW_NORTON7      Norton viscoplasticity, x = (d_eel[6], dp);
+ *   LUPP_LAW_NORTON_AF13  Norton + Armstrong-Frederick kinematic hardening,
+ *                         x = (d_eel[6], dp, d_alpha[6]).
+ * eel = eel_t + d_eel; sig = lambda tr(eel) 1 + 2 mu eel; xi = dev(sig) - 2/3 C
+ * alpha; seq = sqrt(3/2 xi.xi); N = 3/2 xi / seq;
+ * F_e = d_eel + dp N - deps; F_p = dp - dt A seq^m; F_a = d_alpha - dp N +
+ * D dp alpha.  The start is x = 0. At each iterate: a non-finite residual
+ * stops with status 3; ||F||_inf < tol stops with status 0; after maxit linear
+ * solves status 1; a zero pivot status 2.
+ */
+#define LUPP_MAXIT_LIMIT 10000 /* largest accepted maxit (bounds every kernel's run time) */
+#define LUPP_LAW_NORTON7 7
+#define LUPP_LAW_NORTON_AF13 13
+
+typedef struct {
+    int kind;      /* LUPP_LAW_NORTON7 or LUPP_LAW_NORTON_AF13 */
+    double E, nu;  /* Young's modulus, Poisson ratio */
+    double A, m;   /* Norton: dp/dt = A seq^m */
+    double C, D;   /* Armstrong-Frederick modulus and recall (kind 13) */
+    double dt;     /* time step */
+} lupp_law;
+
+typedef struct {
+    int64_t count;        /* number of integration points */
+    int64_t ld;           /* component stride (SoA), >= count */
+    const double *deps;   /* [6][ld]   Kelvin total strain increment */
+    double *state;        /* [kind][ld] eel(6), p, (alpha(6)); updated only where status == 0 */
+    double *sig;          /* [6][ld]   stress at the returned iterate */
+    int32_t *iters;       /* [count]   linear solves performed */
+    int32_t *status;      /* [count]   0 converged, 1 maxit, 2 singular J, 3 non-finite */
+} lupp_points;
+
+int constitutive_update(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law, double tol,
+                        int maxit, void *stream);
+
+/* Human-readable text for a return code (static storage). */
+const char *lupp_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,368 @@
+/* Device-callable LU with partial pivoting for tiny systems (n <= 32), HIP for
+ * gfx950 (CDNA4, wave64).
+ *
+ * This header is the device-side half of the library: a user kernel includes
+ * it and calls a solver from inside its own per-system or per-point code, as
+ * the paper's device-callable solvers are called from inside the fused
+ * constitutive-law kernel (Section 3.2 and Section 3.3; Algorithm 2).
+ *
+ * Arithmetic contract (strict mode, the default):
+ *   - LU with partial pivoting as in Section 2.2: at step k the pivot is the
+ *     candidate of largest magnitude in column k, lowest current row position
+ *     on ties; rows are interchanged (physically in the thread path, logically
+ *     in the lanes path, with the factors written back in the interchanged
+ *     order), multipliers are l_ik = a_ik / a_kk (a true, correctly rounded
+ *     division), and the trailing update is a_ij = a_ij - l_ik * u_kj as one
+ *     rounded multiply followed by one rounded subtract;
+ *   - forward substitution applies b_i = b_i - l_ik * y_k in ascending k, back
+ *     substitution divides by u_jj and then eliminates column j above the
+ *     diagonal, for j descending.
+ * Every element therefore receives the same sequence of rounded operations as
+ * the textbook algorithm, so results are bitwise reproducible across thread
+ * and lanes mappings, layouts, batch compositions and launches. Translation
+ * units that use this header must be compiled with -ffp-contract=off.
+ *
+ * info: 0, or k+1 for the first step k whose pivot is exactly zero (the
+ * factorisation still completes; the solution is then not computed).
+ * ipiv: LAPACK convention, ipiv[k] = 1-based row exchanged with row k.
+ */
+#ifndef LUPP_DEVICE_H
+#define LUPP_DEVICE_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace lupp {
+
+/* ------------------------------------------------------------------------ */
+/* Thread-per-system solver: the whole system lives in one lane's registers. */
+/* Indices into the register arrays are compile-time constants after full    */
+/* unrolling; the data-dependent pivot row is selected with compare/select   */
+/* chains so that nothing spills to scratch memory.                          */
+/* ------------------------------------------------------------------------ */
+
+/* a[j][i] holds element (i, j) (column-major), b the right-hand side.
+ * kFactors: interchange whole rows (all n columns) so that a[][] ends holding
+ * the LAPACK-ordered factors L\U; otherwise only the trailing columns move and
+ * the columns left of the diagonal are garbage on return (enough for a
+ * solve-only caller such as a Newton loop).
+ * On return with info == 0, b holds the solution. ipiv receives the LAPACK
+ * interchange sequence (1-based). */
+/* Compile-time loop: f(integral_constant<int, I>) for I in [B, E). Every
+ * register-array index derived from the loop variable is a constant
+ * expression, so the arrays stay in registers whatever the loop size. */
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+/* Descending variant: I = E-1 down to B. */
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for_down(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, E - 1>{});
+        static_for_down<B, E - 1>(f);
+    }
+}
+
+#define LUPP_SF(v) [&](auto v) __attribute__((always_inline))
+
+template <int N, bool kFactors>
+__device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)[N],
+                                                  int (&ipiv)[N])
+{
+    int info = 0;
+    static_for<0, N>(LUPP_SF(kc) {
+        constexpr int k = decltype(kc)::value;
+        /* pivot search over rows k..N-1 of column k */
+        double best = fabs(a[k][k]);
+        double pv = a[k][k];
+        int p = k;
+        static_for<k + 1, N>(LUPP_SF(ic) {
+            constexpr int i = decltype(ic)::value;
+            const double v = fabs(a[k][i]);
+            const bool gt = v > best;
+            best = gt ? v : best;
+            pv = gt ? a[k][i] : pv;
+            p = gt ? i : p;
+        });
+        ipiv[k] = p + 1;
+        const bool zero = (pv == 0.0);
+        info = (zero && info == 0) ? k + 1 : info;
+
+        /* interchange rows k and p */
+        static_for<(kFactors ? 0 : k), N>(LUPP_SF(jc) {
+            constexpr int j = decltype(jc)::value;
+            const double rk = a[j][k];
+            double rp = rk;
+            static_for<k + 1, N>(LUPP_SF(ic) {
+                constexpr int i = decltype(ic)::value;
+                rp = (p == i) ? a[j][i] : rp;
+            });
+            static_for<k + 1, N>(LUPP_SF(ic) {
+                constexpr int i = decltype(ic)::value;
+                a[j][i] = (p == i) ? rk : a[j][i];
+            });
+            a[j][k] = rp;
+        });
+        {
+            const double rk = b[k];
+            double rp = rk;
+            static_for<k + 1, N>(LUPP_SF(ic) {
+                constexpr int i = decltype(ic)::value;
+                rp = (p == i) ? b[i] : rp;
+            });
+            static_for<k + 1, N>(LUPP_SF(ic) {
+                constexpr int i = decltype(ic)::value;
+                b[i] = (p == i) ? rk : b[i];
+            });
+            b[k] = rp;
+        }
+
+        if (!zero) {
+            /* multipliers, Schur-complement update, forward substitution */
+            static_for<k + 1, N>(LUPP_SF(ic) {
+                constexpr int i = decltype(ic)::value;
+                a[k][i] = a[k][i] / pv;
+            });
+            static_for<k + 1, N>(LUPP_SF(jc) {
+                constexpr int j = decltype(jc)::value;
+                static_for<k + 1, N>(LUPP_SF(ic) {
+                    constexpr int i = decltype(ic)::value;
+                    a[j][i] = a[j][i] - a[k][i] * a[j][k];
+                });
+            });
+            static_for<k + 1, N>(LUPP_SF(ic) {
+                constexpr int i = decltype(ic)::value;
+                b[i] = b[i] - a[k][i] * b[k];
+            });
+        }
+    });
+    if (info == 0) {
+        static_for_down<0, N>(LUPP_SF(jc) {
+            constexpr int j = decltype(jc)::value;
+            b[j] = b[j] / a[j][j];
+            static_for<0, j>(LUPP_SF(ic) {
+                constexpr int i = decltype(ic)::value;
+                b[i] = b[i] - a[j][i] * b[j];
+            });
+        });
+    }
+    return info;
+}
+
+/* Solve-only convenience entry: the device-callable solve of one system held
+ * by the calling thread (a is destroyed). Returns info. */
+template <int N>
+__device__ __forceinline__ int lupp_solve_n(double (&a)[N][N], double (&b)[N], int (&ipiv)[N])
+{
+    return thread_getrf_solve<N, false>(a, b, ipiv);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lanes-per-system solver: T consecutive lanes of a wave64 (a "segment",    */
+/* T a power of two <= 32) cooperate on one system. Lane t owns rows         */
+/* r = t + s*T for slots s = 0..K-1 (round robin, K = ceil(N/T)); a slot     */
+/* with r >= N is a phantom row that takes no part. Rows never move          */
+/* (logical pivoting): pos[s] is the row's current position in LAPACK's      */
+/* interchange order, so the candidates at step k are the rows with          */
+/* pos >= k and ties go to the lowest position. The pivot search is a        */
+/* butterfly reduction inside the segment; the pivot row is broadcast with   */
+/* ds_bpermute.                                                              */
+/* ------------------------------------------------------------------------ */
+template <int N, int T>
+struct lanes_shape {
+    static_assert(T == 1 || T == 2 || T == 4 || T == 8 || T == 16 || T == 32, "T");
+    static constexpr int K = (N + T - 1) / T;
+};
+
+__device__ __forceinline__ double bcast_f64(double v, int src_lane)
+{
+    const int addr = src_lane << 2;
+    const int2 w = *reinterpret_cast<const int2 *>(&v);
+    int2 r;
+    r.x = __builtin_amdgcn_ds_bpermute(addr, w.x);
+    r.y = __builtin_amdgcn_ds_bpermute(addr, w.y);
+    return *reinterpret_cast<const double *>(&r);
+}
+
+__device__ __forceinline__ int bcast_i32(int v, int src_lane)
+{
+    return __builtin_amdgcn_ds_bpermute(src_lane << 2, v);
+}
+
+/* xor-partner exchange inside aligned groups of 2*M lanes */
+template <int M>
+__device__ __forceinline__ int xor_i32(int v)
+{
+    if constexpr (M == 1)  /* quad_perm [1,0,3,2] */
+        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (M == 2)  /* quad_perm [2,3,0,1] */
+        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (M == 4 || M == 8 || M == 16)  /* ds_swizzle bitmask mode: lane ^ M */
+        return __builtin_amdgcn_ds_swizzle(v, (M << 10) | 0x1F);
+    else
+        return __builtin_amdgcn_ds_bpermute(((int)(__lane_id() ^ M)) << 2, v);
+}
+
+template <int M>
+__device__ __forceinline__ double xor_f64(double v)
+{
+    const int2 w = *reinterpret_cast<const int2 *>(&v);
+    int2 r;
+    r.x = xor_i32<M>(w.x);
+    r.y = xor_i32<M>(w.y);
+    return *reinterpret_cast<const double *>(&r);
+}
+
+/* One butterfly round of the (magnitude, key) reduction: keep the larger
+ * magnitude, the lower key on equal magnitudes. */
+template <int M>
+__device__ __forceinline__ void argmax_round(double &mag, int &key)
+{
+    const double om = xor_f64<M>(mag);
+    const int ok = xor_i32<M>(key);
+    const bool take = (om > mag) || (om == mag && ok < key);
+    mag = take ? om : mag;
+    key = take ? ok : key;
+}
+
+/* (magnitude, key) lexicographic max over the T lanes of a segment; every
+ * lane of the segment ends with the result. */
+template <int T>
+__device__ __forceinline__ void segment_argmax(double &mag, int &key)
+{
+    if constexpr (T > 1) argmax_round<1>(mag, key);
+    if constexpr (T > 2) argmax_round<2>(mag, key);
+    if constexpr (T > 4) argmax_round<4>(mag, key);
+    if constexpr (T > 8) argmax_round<8>(mag, key);
+    if constexpr (T > 16) argmax_round<16>(mag, key);
+}
+
+/* Factor (and solve, on info == 0) the system owned by this segment.
+ * a[s][j]: row t+s*T, column j; b[s]: its right-hand side entry; pos[s] must
+ * be initialised to the row index (or -1 for a phantom row). On return
+ * pos[s] is the row's final position: the factors/solution entry held in
+ * slot s belong to row pos[s] of the LAPACK-ordered result. seg_base is the
+ * wave lane of the segment's lane 0. ipiv_k(k, v) is called by every lane
+ * with the segment-uniform interchange ipiv[k] = v (1-based). */
+template <int N, int T, typename IpivSink>
+__device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N],
+                                                 double (&b)[(N + T - 1) / T],
+                                                 int (&pos)[(N + T - 1) / T], int seg_base,
+                                                 IpivSink ipiv_k)
+{
+    constexpr int K = lanes_shape<N, T>::K;
+    const int lane_in_seg = (int)__lane_id() - seg_base;
+    int info = 0;
+    static_for<0, N>(LUPP_SF(kc) {
+        constexpr int k = decltype(kc)::value;
+        /* local candidate: largest |a_rk| among rows with pos >= k, lowest pos on ties */
+        double mag = -1.0;
+        int key = 0x7fffffff;
+        static_for<0, K>(LUPP_SF(sc) {
+            constexpr int s = decltype(sc)::value;
+            const double v = fabs(a[s][k]);
+            const int kk = (pos[s] << 13) | (s << 5) | lane_in_seg;
+            const bool take = (pos[s] >= k) && ((v > mag) || (v == mag && kk < key));
+            mag = take ? v : mag;
+            key = take ? kk : key;
+        });
+        segment_argmax<T>(mag, key);
+        const int tp = key & 31;        /* owning lane within the segment */
+        const int sp = (key >> 5) & 0xff; /* owning slot */
+        const int q = key >> 13;        /* current position of the pivot row */
+        ipiv_k(k, q + 1);
+
+        /* positions: the row at position k moves to q, the pivot row takes k */
+        const bool own = lane_in_seg == tp;
+        static_for<0, K>(LUPP_SF(sc) {
+            constexpr int s = decltype(sc)::value;
+            const int ps = pos[s];
+            pos[s] = (own && sp == s) ? k : ((ps == k) ? q : ps);
+        });
+
+        /* pivot entry: select the slot on every lane, fetch it from lane tp */
+        const int src = seg_base + tp;
+        double sel = a[0][k];
+        static_for<1, K>(LUPP_SF(sc) {
+            constexpr int s = decltype(sc)::value;
+            sel = (sp == s) ? a[s][k] : sel;
+        });
+        const double pv = bcast_f64(sel, src);
+        const bool zero = (mag == 0.0);
+        info = (zero && info == 0) ? k + 1 : info;
+
+        if (!zero) {
+            double l[K];
+            static_for<0, K>(LUPP_SF(sc) {
+                constexpr int s = decltype(sc)::value;
+                l[s] = 0.0;
+                if (pos[s] > k) {
+                    l[s] = a[s][k] / pv;
+                    a[s][k] = l[s];
+                }
+            });
+            static_for<k + 1, N>(LUPP_SF(jc) {
+                constexpr int j = decltype(jc)::value;
+                double us = a[0][j];
+                static_for<1, K>(LUPP_SF(sc) {
+                    constexpr int s = decltype(sc)::value;
+                    us = (sp == s) ? a[s][j] : us;
+                });
+                const double u = bcast_f64(us, src);
+                static_for<0, K>(LUPP_SF(sc) {
+                    constexpr int s = decltype(sc)::value;
+                    if (pos[s] > k) a[s][j] = a[s][j] - l[s] * u;
+                });
+            });
+            double ys = b[0];
+            static_for<1, K>(LUPP_SF(sc) {
+                constexpr int s = decltype(sc)::value;
+                ys = (sp == s) ? b[s] : ys;
+            });
+            const double y = bcast_f64(ys, src);
+            static_for<0, K>(LUPP_SF(sc) {
+                constexpr int s = decltype(sc)::value;
+                if (pos[s] > k) b[s] = b[s] - l[s] * y;
+            });
+        }
+    });
+    if (info == 0) {
+        /* back substitution, column j descending: x_j lives in the row at position j */
+        const uint64_t segmask = ((1ull << T) - 1ull) << (unsigned)seg_base;
+        static_for_down<0, N>(LUPP_SF(jc) {
+            constexpr int j = decltype(jc)::value;
+            bool mine = false;
+            double bs = 0.0, us = 1.0;
+            static_for<0, K>(LUPP_SF(sc) {
+                constexpr int s = decltype(sc)::value;
+                const bool hit = pos[s] == j;
+                mine = mine || hit;
+                bs = hit ? b[s] : bs;
+                us = hit ? a[s][j] : us;
+            });
+            const double xl = bs / us;
+            const uint64_t owners = __ballot(mine) & segmask;
+            const int owner = (int)__builtin_ctzll(owners | (1ull << 63));
+            const double x = bcast_f64(xl, owner);
+            static_for<0, K>(LUPP_SF(sc) {
+                constexpr int s = decltype(sc)::value;
+                if (pos[s] == j) b[s] = x;
+                else if (pos[s] >= 0 && pos[s] < j) b[s] = b[s] - a[s][j] * x;
+            });
+        });
+    }
+    return info;
+}
+
+}  // namespace lupp
+
+#endif

@@ -1,0 +1,196 @@
+/* Fused per-point Newton constitutive update (Section 2.1, equations 1-3;
+ * Section 3.3 and Algorithm 2: the whole Newton loop of every integration
+ * point runs inside one kernel and calls the device-callable LU solver, so
+ * nothing goes back to the host between iterations).
+ *
+ * One lane per integration point; points are stored component-major (SoA):
+ * component c of point p at ptr[c*ld + p].
+ *
+ * Laws (Kelvin-Mandel 6-vectors, backward Euler), unknowns y:
+ *   Norton (7):      y = (d_eel[6], dp)
+ *   Norton + AF(13): y = (d_eel[6], dp, d_alpha[6])
+ *   eel = eel_t + d_eel, sig = lambda tr(eel) 1 + 2 mu eel,
+ *   xi  = dev(sig) - 2/3 C alpha,  seq = sqrt(3/2 xi.xi),  N = 3/2 xi / seq,
+ *   F_e = d_eel + dp N - deps,  F_p = dp - dt A seq^m,
+ *   F_a = d_alpha - dp N + D dp alpha,
+ * with the exact Jacobian of these residuals.
+ */
+#include "internal.h"
+#include "lupp_device.h"
+
+namespace lupp {
+
+struct LawK {
+    double lam, two_mu, dtA, m, c23, D;
+};
+
+/* Residual, Jacobian (J[c][r] = dF_r/dy_c, the solver's column-major form)
+ * and stress at the unknowns y. */
+template <int NU>
+__device__ __forceinline__ void law_assemble(const LawK &P, const double (&de)[6],
+                                             const double (&st)[NU], const double (&y)[NU],
+                                             double (&F)[NU], double (&J)[NU][NU], double (&sig)[6])
+{
+    constexpr bool af = (NU == 13);
+    double e[6], xi[6], al[6], Nv[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) e[i] = st[i] + y[i];
+    const double tr = e[0] + e[1] + e[2];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) sig[i] = P.two_mu * e[i] + (i < 3 ? P.lam * tr : 0.0);
+    const double mean = (sig[0] + sig[1] + sig[2]) / 3.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        xi[i] = sig[i] - (i < 3 ? mean : 0.0);
+        if constexpr (af) {
+            al[i] = st[7 + i] + y[7 + i];
+            xi[i] = xi[i] - P.c23 * al[i];
+        } else {
+            al[i] = 0.0;
+        }
+    }
+    double q = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) q += xi[i] * xi[i];
+    const double seq = sqrt(1.5 * q);
+    const bool pl = seq > 0.0;
+    const double inv = pl ? 1.0 / seq : 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) Nv[i] = pl ? 1.5 * xi[i] / seq : 0.0;
+
+    const double dp = y[6];
+    const double sm1 = pl ? pow(seq, P.m - 1.0) : 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) F[i] = y[i] + dp * Nv[i] - de[i];
+    F[6] = dp - P.dtA * (pl ? pow(seq, P.m) : 0.0);
+    if constexpr (af) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) F[7 + i] = y[7 + i] - dp * Nv[i] + P.D * dp * al[i];
+    }
+
+    /* G = dN/dxi = (3/2 I - N N^T) / seq;  GK = G K (K: deviatoric projector)
+     * so that dN/d(d_eel) = 2 mu GK and dN/d(d_alpha) = -2/3 C G. */
+    double G[6][6], GK[6][6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = 0; b < 6; ++b) G[a][b] = ((a == b ? 1.5 : 0.0) - Nv[a] * Nv[b]) * inv;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        const double rowmean = (G[a][0] + G[a][1] + G[a][2]) / 3.0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) GK[a][b] = G[a][b] - (b < 3 ? rowmean : 0.0);
+    }
+    const double nmean = (Nv[0] + Nv[1] + Nv[2]) / 3.0;
+    const double gd = P.dtA * P.m * sm1; /* d(dt A seq^m)/dseq */
+    const double dp2mu = dp * P.two_mu;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) J[b][a] = (a == b ? 1.0 : 0.0) + dp2mu * GK[a][b];
+        J[b][6] = -gd * P.two_mu * (Nv[b] - (b < 3 ? nmean : 0.0));
+        J[6][b] = Nv[b];
+    }
+    J[6][6] = 1.0;
+    if constexpr (af) {
+        const double cdp = P.c23 * dp;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                J[7 + b][a] = -cdp * G[a][b];                 /* dF_e / d(d_alpha) */
+                J[b][7 + a] = -dp2mu * GK[a][b];              /* dF_a / d(d_eel)   */
+                J[7 + b][7 + a] = (a == b ? 1.0 + P.D * dp : 0.0) + cdp * G[a][b];
+            }
+            J[7 + b][6] = P.c23 * gd * Nv[b];                 /* dF_p / d(d_alpha) */
+            J[6][7 + b] = -Nv[b] + P.D * al[b];               /* dF_a / d(dp)      */
+        }
+    }
+}
+
+template <int NU>
+__global__ void __launch_bounds__(256) k_newton(lupp_points pts, LawK P, double tol, int maxit)
+{
+    const int64_t p0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t rem = pts.count - p0;
+    const uint32_t nvalid = (uint32_t)(rem < (int64_t)blockDim.x ? rem : blockDim.x);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nb = nvalid * 8u, vo = tid * 8u;
+
+    double de[6], st[NU], y[NU], F[NU], sig[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) de[c] = buf_load_f64(make_rsrc(pts.deps + c * pts.ld + p0, nb), vo, 0);
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+        st[c] = buf_load_f64(make_rsrc(pts.state + c * pts.ld + p0, nb), vo, 0);
+        y[c] = 0.0;
+    }
+
+    int status = 1, it = 0;
+    for (;; ++it) {
+        double J[NU][NU];
+        law_assemble<NU>(P, de, st, y, F, J, sig);
+        bool finite = true;
+        double nrm = 0.0;
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+            finite = finite && __builtin_isfinite(F[i]);
+            nrm = fmax(nrm, fabs(F[i]));
+        }
+        if (!finite) { status = 3; break; }
+        if (nrm < tol) { status = 0; break; }
+        if (it == maxit) { status = 1; break; }
+        double dx[NU];
+        int piv[NU];
+#pragma unroll
+        for (int i = 0; i < NU; ++i) dx[i] = -F[i];
+        if (thread_getrf_solve<NU, false>(J, dx, piv) != 0) { status = 2; break; }
+#pragma unroll
+        for (int i = 0; i < NU; ++i) y[i] = y[i] + dx[i];
+    }
+
+#pragma unroll
+    for (int c = 0; c < 6; ++c) buf_store_f64(make_rsrc(pts.sig + c * pts.ld + p0, nb), vo, 0, sig[c]);
+    const uint32_t vs = status == 0 ? vo : kOutOfRange;
+#pragma unroll
+    for (int c = 0; c < NU; ++c)
+        buf_store_f64(make_rsrc(pts.state + c * pts.ld + p0, nb), vs, 0, st[c] + y[c]);
+    buf_store_i32(make_rsrc(pts.iters + p0, nvalid * 4u), tid * 4u, 0, it);
+    buf_store_i32(make_rsrc(pts.status + p0, nvalid * 4u), tid * 4u, 0, status);
+}
+
+static LawK law_constants(const lupp_law *law)
+{
+    LawK P;
+    P.lam = law->E * law->nu / ((1.0 + law->nu) * (1.0 - 2.0 * law->nu));
+    P.two_mu = law->E / (1.0 + law->nu);
+    P.dtA = law->dt * law->A;
+    P.m = law->m;
+    P.c23 = law->kind == LUPP_LAW_NORTON_AF13 ? 2.0 / 3.0 * law->C : 0.0;
+    P.D = law->kind == LUPP_LAW_NORTON_AF13 ? law->D : 0.0;
+    return P;
+}
+
+int constitutive_launch(const lupp_points *pts, const lupp_law *law, double tol, int maxit,
+                        hipStream_t stream)
+{
+    const LawK P = law_constants(law);
+    const int threads = 256;
+    const int64_t blocks = (pts->count + threads - 1) / threads;
+    if (law->kind == LUPP_LAW_NORTON7)
+        hipLaunchKernelGGL((k_newton<7>), dim3((unsigned)blocks), dim3(threads), 0, stream, *pts, P,
+                           tol, maxit);
+    else
+        hipLaunchKernelGGL((k_newton<13>), dim3((unsigned)blocks), dim3(threads), 0, stream, *pts,
+                           P, tol, maxit);
+    return hip_err(hipGetLastError());
+}
+
+const void *constitutive_kernel_symbol(int kind)
+{
+    if (kind == LUPP_LAW_NORTON7) return reinterpret_cast<const void *>(&k_newton<7>);
+    if (kind == LUPP_LAW_NORTON_AF13) return reinterpret_cast<const void *>(&k_newton<13>);
+    return nullptr;
+}
+
+}  // namespace lupp

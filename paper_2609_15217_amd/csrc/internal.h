@@ -1,0 +1,99 @@
+/* Internal declarations shared by the library's translation units. */
+#ifndef LUPP_INTERNAL_H
+#define LUPP_INTERNAL_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lupp.h"
+
+namespace lupp {
+
+/* Arguments of one batched-solve launch (layout-generic). */
+struct SolveArgs {
+    int64_t batch;
+    double *A;
+    int64_t lda;
+    int64_t sA;  /* AoS: system stride; SoA: ldbatch */
+    double *b;
+    int64_t sB;  /* AoS: system stride; SoA: component stride */
+    int32_t *ipiv;
+    int32_t *info;
+};
+
+/* Enqueue one batched-solve kernel: layout LUPP_AOS/LUPP_SOA, factors =
+ * write L\U back, wpb = wave64s per workgroup (0: default). */
+typedef hipError_t (*LaunchFn)(const SolveArgs &, int layout, bool factors, int wpb,
+                               hipStream_t);
+
+/* Kernel lookup (registry.cpp): nullptr if the variant is not compiled. */
+LaunchFn thread_launcher(int n);
+LaunchFn lanes_launcher(int n, int lanes);
+const void *thread_kernel_symbol(int n);
+const void *lanes_kernel_symbol(int n, int lanes);
+/* Segment widths compiled for size n (ascending), returns the count. */
+int lanes_widths(int n, int *out, int cap);
+constexpr int kThreadMaxN = 13;
+
+/* Constitutive update launcher (constitutive.hip). */
+int constitutive_launch(const lupp_points *pts, const lupp_law *law, double tol, int maxit,
+                        hipStream_t stream);
+const void *constitutive_kernel_symbol(int kind);
+
+/* Ragged batch (ragged.hip). */
+struct lupp_ragged_ws;
+int ragged_launch(lupp_ctx *ctx, int64_t batch, const int32_t *n, const int64_t *offA,
+                  const int64_t *offB, double *A, double *b, int32_t *ipiv, int32_t *info,
+                  bool factors, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Device-side memory access through buffer resources.                      */
+/*                                                                          */
+/* A buffer resource is a 128-bit descriptor (base, size) held in SGPRs; a   */
+/* load or store adds a 32-bit per-lane byte offset (VGPR) and a 32-bit      */
+/* uniform offset (SGPR). Per-element addresses therefore cost no VGPRs, and */
+/* an access at or beyond `bytes` reads 0 / writes nothing, which retires    */
+/* the lanes past the end of a batch without branches.                      */
+/* ------------------------------------------------------------------------ */
+typedef int lupp_v2i __attribute__((ext_vector_type(2)));
+
+/* word 3 of a raw (untyped) buffer descriptor on gfx9-family GPUs: 32-bit
+ * data format, no swizzle */
+constexpr int kBufferWord3 = 0x00020000;
+
+/* A per-lane byte offset that is out of range for every descriptor the
+ * library builds (their extents stay below 2^31 bytes): loads return zero and
+ * stores are dropped. */
+constexpr uint32_t kOutOfRange = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             kBufferWord3);
+}
+
+__device__ __forceinline__ double buf_load_f64(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                               uint32_t soff)
+{
+    lupp_v2i v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+    return __builtin_bit_cast(double, v);
+}
+
+__device__ __forceinline__ void buf_store_f64(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                              uint32_t soff, double x)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(lupp_v2i, x), r, (int)voff,
+                                          (int)soff, 0);
+}
+
+__device__ __forceinline__ void buf_store_i32(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                              uint32_t soff, int x)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(x, r, (int)voff, (int)soff, 0);
+}
+
+inline int hip_err(hipError_t e) { return e == hipSuccess ? 0 : LUPP_E_HIP_BASE - (int)e; }
+
+}  // namespace lupp
+
+#endif

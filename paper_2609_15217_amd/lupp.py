@@ -1,0 +1,245 @@
+"""Thin ctypes binding of liblupp (the C ABI declared in include/lupp.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of liblupp.so. Tensors are passed by device pointer
+(``tensor.data_ptr()``) and streams by handle
+(``torch.cuda.current_stream().cuda_stream``). PyTorch is used for device
+memory and streams only.
+
+The library must have been built (``python -m paper_2609_15217_amd.build``);
+importing this module without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime the library then shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblupp.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2609_15217_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+LUPP_AOS, LUPP_SOA = 0, 1
+LUPP_KEEP_A = 1
+LUPP_VARIANT_AUTO, LUPP_VARIANT_THREAD, LUPP_VARIANT_LANES = 0, 1, 2
+LUPP_LAW_NORTON7, LUPP_LAW_NORTON_AF13 = 7, 13
+LUPP_E_UNSUPPORTED, LUPP_E_NOMEM, LUPP_E_HIP_BASE = -900, -901, -1000
+
+_P = ctypes.c_void_p
+_i64 = ctypes.c_int64
+
+
+class lupp_law(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("E", ctypes.c_double), ("nu", ctypes.c_double),
+                ("A", ctypes.c_double), ("m", ctypes.c_double), ("C", ctypes.c_double),
+                ("D", ctypes.c_double), ("dt", ctypes.c_double)]
+
+
+class lupp_points(ctypes.Structure):
+    _fields_ = [("count", _i64), ("ld", _i64), ("deps", _P), ("state", _P), ("sig", _P),
+                ("iters", _P), ("status", _P)]
+
+
+class lupp_kernel_info(ctypes.Structure):
+    _fields_ = [("vgprs", ctypes.c_int), ("agprs", ctypes.c_int), ("sgprs", ctypes.c_int),
+                ("scratch_bytes", ctypes.c_int), ("lds_bytes", ctypes.c_int),
+                ("max_threads", ctypes.c_int)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_lupp_create = _sig("lupp_create", ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int])
+_lupp_destroy = _sig("lupp_destroy", None, [_P])
+_lupp_batched_solve = _sig("lupp_batched_solve", ctypes.c_int,
+                           [_P, ctypes.c_int, _i64, ctypes.c_int, _P, _i64, _i64, _P, _i64, _P, _P,
+                            ctypes.c_uint, _P])
+_lupp_batched_solve_ragged = _sig("lupp_batched_solve_ragged", ctypes.c_int,
+                                  [_P, _i64, _P, _P, _P, _P, _P, _P, _P, ctypes.c_uint, _P])
+_lupp_force_variant = _sig("lupp_force_variant", ctypes.c_int,
+                           [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int])
+_lupp_set_dispatch = _sig("lupp_set_dispatch", ctypes.c_int,
+                          [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int])
+_lupp_get_dispatch = _sig("lupp_get_dispatch", ctypes.c_int,
+                          [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)])
+_lupp_variant_info = _sig("lupp_variant_info", ctypes.c_int,
+                          [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                           ctypes.POINTER(lupp_kernel_info)])
+_constitutive_update = _sig("constitutive_update", ctypes.c_int,
+                            [_P, ctypes.POINTER(lupp_points), ctypes.POINTER(lupp_law),
+                             ctypes.c_double, ctypes.c_int, _P])
+_lupp_error_string = _sig("lupp_error_string", ctypes.c_char_p, [ctypes.c_int])
+_lupp_check_solve_args = _sig("lupp_check_solve_args", ctypes.c_int,
+                              [ctypes.c_int, _i64, ctypes.c_int, _P, _i64, _i64, _P, _i64, _P, _P,
+                               ctypes.c_uint])
+
+EXPORTED = ["lupp_create", "lupp_destroy", "lupp_batched_solve", "lupp_batched_solve_ragged",
+            "lupp_force_variant", "lupp_set_dispatch", "lupp_get_dispatch", "lupp_variant_info",
+            "constitutive_update", "lupp_error_string", "lupp_check_solve_args"]
+
+
+class LuppError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {lupp_error_string(code)} (code {code})")
+        self.code = code
+
+
+def _check(rc: int, what: str) -> int:
+    if rc != 0:
+        raise LuppError(rc, what)
+    return rc
+
+
+def _ptr(x) -> _P:
+    if x is None:
+        return _P(0)
+    if isinstance(x, int):
+        return _P(x)
+    return _P(x.data_ptr())
+
+
+def _stream(stream) -> _P:
+    if stream is None:
+        return _P(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return _P(stream)
+    return _P(stream.cuda_stream)
+
+
+def lupp_error_string(code: int) -> str:
+    return _lupp_error_string(code).decode()
+
+
+class Context:
+    """Owns a lupp_ctx (dispatch table, device workspace) for one device."""
+
+    def __init__(self, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        h = _P()
+        _check(_lupp_create(ctypes.byref(h), device), "lupp_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _lupp_destroy(self.handle)
+            self.handle = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lupp_create(device: int | None = None) -> Context:
+    return Context(device)
+
+
+def lupp_destroy(ctx: Context):
+    ctx.close()
+
+
+def lupp_batched_solve(ctx: Context, n: int, batch: int, layout: int, A, lda: int, strideA: int,
+                       b, strideB: int, ipiv, info, flags: int = 0, stream=None) -> int:
+    """Raw C-ABI call: returns the library's code (0, -k, LUPP_E_*)."""
+    return _lupp_batched_solve(ctx.handle, n, batch, layout, _ptr(A), lda, strideA, _ptr(b),
+                               strideB, _ptr(ipiv), _ptr(info), flags, _stream(stream))
+
+
+def lupp_batched_solve_ragged(ctx: Context, batch: int, n, offA, offB, A, b, ipiv, info,
+                              flags: int = 0, stream=None) -> int:
+    return _lupp_batched_solve_ragged(ctx.handle, batch, _ptr(n), _ptr(offA), _ptr(offB), _ptr(A),
+                                      _ptr(b), _ptr(ipiv), _ptr(info), flags, _stream(stream))
+
+
+def lupp_check_solve_args(n: int, batch: int, layout: int, A, lda: int, strideA: int, b,
+                          strideB: int, ipiv, info, flags: int = 0) -> int:
+    return _lupp_check_solve_args(n, batch, layout, _ptr(A), lda, strideA, _ptr(b), strideB,
+                                  _ptr(ipiv), _ptr(info), flags)
+
+
+def lupp_force_variant(ctx: Context, variant: int, lanes: int = 0, wpb: int = 0) -> int:
+    return _lupp_force_variant(ctx.handle, variant, lanes, wpb)
+
+
+def lupp_set_dispatch(ctx: Context, n: int, layout: int, variant: int, lanes: int, wpb: int) -> int:
+    return _lupp_set_dispatch(ctx.handle, n, layout, variant, lanes, wpb)
+
+
+def lupp_get_dispatch(ctx: Context, n: int, layout: int):
+    v, l, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(_lupp_get_dispatch(ctx.handle, n, layout, ctypes.byref(v), ctypes.byref(l),
+                              ctypes.byref(w)), "lupp_get_dispatch")
+    return v.value, l.value, w.value
+
+
+def lupp_variant_info(n: int, layout: int, variant: int, lanes: int = 0, keep_a: int = 0):
+    out = lupp_kernel_info()
+    rc = _lupp_variant_info(n, layout, variant, lanes, keep_a, ctypes.byref(out))
+    if rc != 0:
+        return None
+    return {f: getattr(out, f) for f, _ in lupp_kernel_info._fields_}
+
+
+def constitutive_update(ctx: Context, pts: lupp_points, law: lupp_law, tol: float, maxit: int,
+                        stream=None) -> int:
+    return _constitutive_update(ctx.handle, ctypes.byref(pts), ctypes.byref(law), tol, maxit,
+                                _stream(stream))
+
+
+# --------------------------------------------------------------------------
+# Tensor-level helpers (marshalling only)
+# --------------------------------------------------------------------------
+def batched_solve(ctx: Context, A: torch.Tensor, b: torch.Tensor, layout: int = LUPP_AOS,
+                  keep_a: bool = False, ipiv: torch.Tensor | None = None,
+                  info: torch.Tensor | None = None, stream=None):
+    """In-place batched solve of device tensors.
+    AoS: A (batch, n, n) read [s][j][i] (column-major per system), b (batch, n).
+    SoA: A (n, n, batch) read [j][i][s], b (n, batch).
+    Returns (ipiv, info) int32 device tensors in the matching layout."""
+    assert A.is_cuda and A.dtype == torch.float64 and A.is_contiguous()
+    assert b.is_cuda and b.dtype == torch.float64 and b.is_contiguous()
+    if layout == LUPP_AOS:
+        batch, n = A.shape[0], A.shape[1]
+        sA, sB = n * n, n
+        pshape = (batch, n)
+    else:
+        n, batch = A.shape[0], A.shape[2]
+        sA, sB = batch, batch
+        pshape = (n, batch)
+    if ipiv is None:
+        ipiv = torch.empty(pshape, dtype=torch.int32, device=A.device)
+    if info is None:
+        info = torch.empty(batch, dtype=torch.int32, device=A.device)
+    rc = lupp_batched_solve(ctx, n, batch, layout, A, n, sA, b, sB, ipiv, info,
+                            LUPP_KEEP_A if keep_a else 0, stream)
+    _check(rc, "lupp_batched_solve")
+    return ipiv, info
+
+
+def make_law(kind: int = 7, E=200e3, nu=0.3, A=1e-8, m=5.0, C=1e4, D=100.0, dt=1e-2) -> lupp_law:
+    return lupp_law(kind, E, nu, A, m, C, D, dt)
+
+
+def points(deps: torch.Tensor, state: torch.Tensor, sig: torch.Tensor, iters: torch.Tensor,
+           status: torch.Tensor) -> lupp_points:
+    """SoA point buffers: deps (6, ld), state (kind, ld), sig (6, ld),
+    iters/status (count,) int32."""
+    count = iters.shape[0]
+    ld = deps.shape[1]
+    for t in (deps, state, sig):
+        assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.shape[1] == ld
+    return lupp_points(count, ld, deps.data_ptr(), state.data_ptr(), sig.data_ptr(),
+                       iters.data_ptr(), status.data_ptr())
