@@ -1,0 +1,338 @@
+"""Benchmark: batched FP64 LU with partial pivoting + substitution for tiny
+systems, and the fused Newton constitutive update, on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+One step = one pass of the standalone-solve sweep: 2^20 independent systems
+for each n in {4, 8, 12, 16, 24, 32} (A ~ N(0,1) resampled while
+cond2(A) > 1e4, b = A x_true, x_true ~ U(-1,1)), solved in the interleaved
+SoA layout and in the AoS layout (24 launches of lupp_batched_solve). The
+solve is in place, so every step starts from inputs restored from a pristine
+device copy outside the timed region. `value` is systems solved per second
+over the timed steps.
+
+Also reported: the fused Newton update (2^20 points, Norton 7x7 and
+Norton+Armstrong-Frederick 13x13), per-call latency p50/p99 of a 4096-system
+n = 8 solve, per-kernel durations and roofline fractions, and the CPU oracle
+timed on this host on a bounded sample.
+
+Profiling helpers (for rocprofv3):
+    python bench.py --only 32:soa --reps 20     run one (n, layout) kernel only
+    python bench.py --copy-calibration          a plain 2 GiB device copy
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 systems solved/s (n=8..32) + Newton updates/s; p50/p99 latency"
+SIZES = (4, 8, 12, 16, 24, 32)
+BATCH = 1 << 20
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def bytes_per_system(n: int) -> int:
+    """dgesv traffic: read A and b, write L\\U, x, ipiv (int32) and info."""
+    return 16 * n * n + 20 * n + 4
+
+
+def flops_per_system(n: int) -> int:
+    """Factorisation sum_{m=1}^{n-1} (m + 2 m^2) plus the two triangular
+    solves 2 n^2 - n."""
+    return sum(m + 2 * m * m for m in range(1, n)) + 2 * n * n - n
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for d in ("include", os.path.join("paper_2609_15217_amd", "csrc")):
+        p = os.path.join(ROOT, d)
+        for name in sorted(os.listdir(p)):
+            h.update(open(os.path.join(p, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_key: str):
+    """HBM traffic per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except ValueError:
+        return None
+    rec = data.get(kernel_key)
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-newton", action="store_true")
+    ap.add_argument("--only", default=None, help="n:layout, e.g. 32:soa")
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: every system and integration point is independent, "
+              "so the path runs on one GPU's share; runs on more than one GPU are not part of "
+              "this build.", flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2609_15217_amd.lupp as L
+    from workloads import aos_to_soa, newton_points, systems
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float64, device=dev).fill_(1.0)  # 2 GiB
+        dst = torch.empty_like(src)
+        for _ in range(args.reps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": src.numel() * 8,
+                          "reps": args.reps}), flush=True)
+        return
+
+    ctx = L.Context(0)
+    sizes = SIZES
+    layouts = ("soa", "aos")
+    if args.only:
+        n_s, lay = args.only.split(":")
+        sizes, layouts = (int(n_s),), (lay,)
+
+    # ---------------------------------------------------------------- inputs
+    t0 = time.time()
+    pristine, work, host = {}, {}, {}
+    for n in sizes:
+        A, b, _ = systems(n, BATCH, seed=2000 + n, kappa_max=1e4)
+        host[n] = (A, b)
+        tA = torch.from_numpy(A).to(dev)
+        tb = torch.from_numpy(b).to(dev)
+        for lay in layouts:
+            if lay == "soa":
+                pA = tA.permute(1, 2, 0).contiguous()
+                pb = tb.t().contiguous()
+            else:
+                pA, pb = tA, tb
+            pristine[(n, lay)] = (pA, pb)
+            wA, wb = torch.empty_like(pA), torch.empty_like(pb)
+            pshape = (n, BATCH) if lay == "soa" else (BATCH, n)
+            ipiv = torch.empty(pshape, dtype=torch.int32, device=dev)
+            info = torch.empty(BATCH, dtype=torch.int32, device=dev)
+            work[(n, lay)] = (wA, wb, ipiv, info)
+        del tA, tb
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.time() - t0:.1f}s")
+
+    def restore():
+        for key, (pA, pb) in pristine.items():
+            wA, wb, _, _ = work[key]
+            wA.copy_(pA)
+            wb.copy_(pb)
+
+    def launch(key):
+        n, lay = key
+        wA, wb, ipiv, info = work[key]
+        layout = L.LUPP_SOA if lay == "soa" else L.LUPP_AOS
+        sA, sB = (BATCH, BATCH) if lay == "soa" else (n * n, n)
+        rc = L.lupp_batched_solve(ctx, n, BATCH, layout, wA, n, sA, wb, sB, ipiv, info, 0, stream)
+        if rc != 0:
+            raise RuntimeError(f"lupp_batched_solve n={n} {lay}: {L.lupp_error_string(rc)}")
+
+    keys = [(n, lay) for n in sizes for lay in layouts]
+
+    if args.only:
+        for r in range(args.reps):
+            restore()
+            launch(keys[0])
+        torch.cuda.synchronize()
+        log(f"--only {args.only}: {args.reps} launches done")
+        return
+
+    # ------------------------------------------------------------- sweep
+    ev = {k: [] for k in keys}
+    for w in range(args.warmup):
+        restore()
+        for k in keys:
+            launch(k)
+        torch.cuda.synchronize()
+        log(f"warmup step {w + 1}/{args.warmup} done")
+    total = 0.0
+    for s in range(args.steps):
+        restore()
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in keys:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            launch(k)
+            e1.record(stream)
+            ev[k].append((e0, e1))
+        torch.cuda.synchronize()
+        total += time.perf_counter() - t_start
+        log(f"step {s + 1}/{args.steps} done")
+    systems_per_step = len(keys) * BATCH
+    value = systems_per_step * args.steps / total
+    ms_per_step = 1000.0 * total / args.steps
+
+    # correctness guard: every system solved
+    for k in keys:
+        info = work[k][3]
+        bad = int((info != 0).sum().item())
+        if bad:
+            raise RuntimeError(f"{bad} systems with info != 0 for {k}")
+
+    per_kernel = []
+    for k in keys:
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev[k]]))
+        n, lay = k
+        gbs = bytes_per_system(n) * BATCH / (ms * 1e-3) / 1e9
+        tfl = flops_per_system(n) * BATCH / (ms * 1e-3) / 1e12
+        v, lanes, wpb = L.lupp_get_dispatch(ctx, n, L.LUPP_SOA if lay == "soa" else L.LUPP_AOS)
+        per_kernel.append({"n": n, "layout": lay, "ms": round(ms, 4),
+                           "systems_per_s": round(BATCH / (ms * 1e-3)),
+                           "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                           "fp64_TFLOPs": round(tfl, 3),
+                           "variant": "thread" if v == 1 else f"lanes{lanes}", "wpb": wpb})
+    dom = max(per_kernel, key=lambda r: r["ms"])
+    dom_key = f"lupp_n{dom['n']}_{dom['layout']}"
+    achieved = dom["GBps"]
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": load_traffic(dom_key), "kernel": dom_key,
+                "algorithmic_bytes_per_launch": bytes_per_system(dom["n"]) * BATCH}
+
+    # ------------------------------------------------------------- latency
+    lat = {}
+    A1, b1, _ = systems(8, 4096, seed=1)
+    pA1 = torch.from_numpy(A1).to(dev)
+    pb1 = torch.from_numpy(b1).to(dev)
+    wA1, wb1 = torch.empty_like(pA1), torch.empty_like(pb1)
+    ip1 = torch.empty((4096, 8), dtype=torch.int32, device=dev)
+    in1 = torch.empty(4096, dtype=torch.int32, device=dev)
+    samples = []
+    for r in range(220):
+        wA1.copy_(pA1)
+        wb1.copy_(pb1)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rc = L.lupp_batched_solve(ctx, 8, 4096, L.LUPP_AOS, wA1, 8, 64, wb1, 8, ip1, in1, 0, stream)
+        e1.record(stream)
+        assert rc == 0
+        samples.append((e0, e1))
+    torch.cuda.synchronize()
+    us = np.array([a.elapsed_time(b) * 1000.0 for a, b in samples[20:]])
+    lat = {"workload": "4096 systems, n=8, AoS, N(0,1), seed 1", "p50_us": round(float(np.percentile(us, 50)), 2),
+           "p99_us": round(float(np.percentile(us, 99)), 2),
+           "systems_per_s_at_p50": round(4096 / (np.percentile(us, 50) * 1e-6))}
+    log(f"latency p50 {lat['p50_us']} us")
+
+    # ------------------------------------------------------------- Newton
+    newton = {}
+    if not args.no_newton:
+        count = 1 << 20
+        deps = newton_points(count, seed=4)
+        d = torch.from_numpy(deps.T.copy()).to(dev)
+        for kind in (7, 13):
+            st = torch.zeros((kind, count), dtype=torch.float64, device=dev)
+            sig = torch.empty((6, count), dtype=torch.float64, device=dev)
+            it = torch.empty(count, dtype=torch.int32, device=dev)
+            stt = torch.empty(count, dtype=torch.int32, device=dev)
+            pts = L.points(d, st, sig, it, stt)
+            law = L.make_law(kind)
+            times = []
+            for r in range(args.warmup + args.steps):
+                st.zero_()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                rc = L.constitutive_update(ctx, pts, law, 1e-12, 20, stream)
+                e1.record(stream)
+                assert rc == 0
+                torch.cuda.synchronize()
+                if r >= args.warmup:
+                    times.append(e0.elapsed_time(e1))
+            ms = float(np.mean(times))
+            its = it.double().sum().item()
+            conv = int((stt == 0).sum().item())
+            newton[f"norton{kind}"] = {"points": count, "ms": round(ms, 3),
+                                       "updates_per_s": round(count / (ms * 1e-3)),
+                                       "newton_iterations_per_s": round(its / (ms * 1e-3)),
+                                       "mean_solves_per_point": round(its / count, 3),
+                                       "converged": conv}
+            log(f"newton {kind}: {ms:.2f} ms")
+
+    # ------------------------------------------------------------- CPU oracle
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        cores = min(16, os.cpu_count() or 1)
+        S = 1 << 19
+        t = time.perf_counter()
+        for n in sizes:
+            A, b = host[n]
+            oracle.gesv_batch(A[:S], b[:S], threads=cores)
+        dt = time.perf_counter() - t
+        cpu = {"value": round(len(sizes) * S / dt), "unit": "systems/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"first {S} systems of each n in {list(sizes)} (AoS; the oracle has one "
+                         f"layout), same inputs as the GPU sweep, {dt:.1f}s wall"}
+        if not args.no_newton:
+            P = 1 << 16
+            deps = newton_points(P, seed=4)
+            nt = {}
+            for kind in (7, 13):
+                t = time.perf_counter()
+                oracle.constitutive_update(oracle.Law(kind=kind), deps, threads=cores)
+                nt[f"norton{kind}_updates_per_s"] = round(P / (time.perf_counter() - t))
+            cpu["newton"] = nt
+        log(f"cpu oracle {cpu['value']} systems/s on {cores} threads")
+
+    out = {
+        "metric": METRIC, "value": round(value), "unit": "systems/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "LUpp sweep: 2^20 FP64 systems for each n in {4,8,12,16,24,32}, "
+                               "A ~ N(0,1) rejected if cond2 > 1e4, b = A x_true, x_true ~ U(-1,1), "
+                               "SoA and AoS, one RHS",
+                   "batch_per_n": BATCH, "n": list(sizes), "layouts": list(layouts),
+                   "mode": "strict (bitwise-reproducible, no FMA, true division)"},
+        "roofline": roofline,
+        "newton": newton,
+        "latency": lat,
+        "per_kernel": per_kernel,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
