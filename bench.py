@@ -214,7 +214,7 @@ def main():
         n, lay = k
         gbs = bytes_per_system(n) * BATCH / (ms * 1e-3) / 1e9
         tfl = flops_per_system(n) * BATCH / (ms * 1e-3) / 1e12
-        v, lanes, wpb = L.lupp_get_dispatch(ctx, n, L.LUPP_SOA if lay == "soa" else L.LUPP_AOS)
+        v, lanes, wpb = L.lupp_get_dispatch(ctx, n, L.LUPP_SOA if lay == "soa" else L.LUPP_AOS, BATCH)
         per_kernel.append({"n": n, "layout": lay, "ms": round(ms, 4),
                            "systems_per_s": round(BATCH / (ms * 1e-3)),
                            "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),

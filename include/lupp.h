@@ -115,10 +115,25 @@ int lupp_batched_solve_ragged(lupp_ctx *ctx, int64_t batch, const int32_t *n,
  * if a later call's n cannot be served by the forced variant. */
 int lupp_force_variant(lupp_ctx *ctx, int variant, int lanes, int wpb);
 
-/* Set the dispatch-table entry used for size n and layout: the autotuner
- * writes its choice through this call. */
-int lupp_set_dispatch(lupp_ctx *ctx, int n, int layout, int variant, int lanes, int wpb);
-int lupp_get_dispatch(lupp_ctx *ctx, int n, int layout, int *variant, int *lanes, int *wpb);
+/* Set / read the dispatch-table entry used for size n, layout and batches of
+ * the size class of `batch` (below 32768 systems, or from 32768 on). The
+ * table starts from the entries the autotuner measured on gfx950. */
+int lupp_set_dispatch(lupp_ctx *ctx, int n, int layout, int64_t batch, int variant, int lanes,
+                      int wpb);
+int lupp_get_dispatch(lupp_ctx *ctx, int n, int layout, int64_t batch, int *variant, int *lanes,
+                      int *wpb);
+
+/* Autotune the dispatch entry for size n, layout and the size class of batch
+ * (Section 4.1: launch
+ * configuration chosen per problem by measurement): time every compiled
+ * kernel variant and workgroup size on a device copy of the caller's batch
+ * (A and b are only read), keep the fastest in the context's dispatch table,
+ * and report it. Synchronous: allocates and frees its own device workspace
+ * (the size of A, b, ipiv and info) and waits for `stream`. reps >= 1 timed
+ * launches per candidate after one warm-up; the median is compared. */
+int lupp_autotune(lupp_ctx *ctx, int n, int64_t batch, int layout, const double *A, int64_t lda,
+                  int64_t strideA, const double *b, int64_t strideB, int reps, int *variant,
+                  int *lanes, int *wpb, float *ms, void *stream);
 
 /* Compile-time resources of one kernel variant: VGPRs, AGPRs and SGPRs per
  * lane, private (scratch) bytes per lane, and LDS bytes per workgroup.

@@ -186,11 +186,11 @@ struct lanes_shape {
 __device__ __forceinline__ double bcast_f64(double v, int src_lane)
 {
     const int addr = src_lane << 2;
-    const int2 w = *reinterpret_cast<const int2 *>(&v);
+    const int2 w = __builtin_bit_cast(int2, v);
     int2 r;
     r.x = __builtin_amdgcn_ds_bpermute(addr, w.x);
     r.y = __builtin_amdgcn_ds_bpermute(addr, w.y);
-    return *reinterpret_cast<const double *>(&r);
+    return __builtin_bit_cast(double, r);
 }
 
 __device__ __forceinline__ int bcast_i32(int v, int src_lane)
@@ -198,52 +198,66 @@ __device__ __forceinline__ int bcast_i32(int v, int src_lane)
     return __builtin_amdgcn_ds_bpermute(src_lane << 2, v);
 }
 
-/* xor-partner exchange inside aligned groups of 2*M lanes */
-template <int M>
-__device__ __forceinline__ int xor_i32(int v)
+/* Butterfly exchange inside aligned groups of 2^(L+1) lanes, all on the VALU:
+ * L = 0, 1: quad permutes (lane ^ 1, lane ^ 2); L = 2: mirror inside 8 lanes;
+ * L = 3: mirror inside 16 lanes; L = 4: rows of 16 exchanged in pairs.
+ * Each lane receives the value of a partner in the other half of its group;
+ * the callers combine own and partner values with a commutative operation, so
+ * after levels 0..L every lane of a group holds the group's result. */
+template <int L>
+__device__ __forceinline__ void pair_u32(unsigned v, unsigned &a, unsigned &b)
 {
-    if constexpr (M == 1)  /* quad_perm [1,0,3,2] */
-        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
-    else if constexpr (M == 2)  /* quad_perm [2,3,0,1] */
-        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
-    else if constexpr (M == 4 || M == 8 || M == 16)  /* ds_swizzle bitmask mode: lane ^ M */
-        return __builtin_amdgcn_ds_swizzle(v, (M << 10) | 0x1F);
-    else
-        return __builtin_amdgcn_ds_bpermute(((int)(__lane_id() ^ M)) << 2, v);
+    if constexpr (L == 0) { a = v; b = __builtin_amdgcn_update_dpp(0u, v, 0xB1, 0xF, 0xF, false); }
+    else if constexpr (L == 1) { a = v; b = __builtin_amdgcn_update_dpp(0u, v, 0x4E, 0xF, 0xF, false); }
+    else if constexpr (L == 2) { a = v; b = __builtin_amdgcn_update_dpp(0u, v, 0x141, 0xF, 0xF, false); }
+    else if constexpr (L == 3) { a = v; b = __builtin_amdgcn_update_dpp(0u, v, 0x140, 0xF, 0xF, false); }
+    else {
+        /* {a, b} = {own, partner} in some order */
+        auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        a = r[0];
+        b = r[1];
+    }
 }
 
-template <int M>
-__device__ __forceinline__ double xor_f64(double v)
+template <int L>
+__device__ __forceinline__ double max_round(double v)
 {
-    const int2 w = *reinterpret_cast<const int2 *>(&v);
-    int2 r;
-    r.x = xor_i32<M>(w.x);
-    r.y = xor_i32<M>(w.y);
-    return *reinterpret_cast<const double *>(&r);
+    const uint2 w = __builtin_bit_cast(uint2, v);
+    uint2 a, b;
+    pair_u32<L>(w.x, a.x, b.x);
+    pair_u32<L>(w.y, a.y, b.y);
+    return fmax(__builtin_bit_cast(double, a), __builtin_bit_cast(double, b));
 }
 
-/* One butterfly round of the (magnitude, key) reduction: keep the larger
- * magnitude, the lower key on equal magnitudes. */
-template <int M>
-__device__ __forceinline__ void argmax_round(double &mag, int &key)
+template <int L>
+__device__ __forceinline__ int min_round(int v)
 {
-    const double om = xor_f64<M>(mag);
-    const int ok = xor_i32<M>(key);
-    const bool take = (om > mag) || (om == mag && ok < key);
-    mag = take ? om : mag;
-    key = take ? ok : key;
+    unsigned a, b;
+    pair_u32<L>((unsigned)v, a, b);
+    return min((int)a, (int)b);
 }
 
-/* (magnitude, key) lexicographic max over the T lanes of a segment; every
- * lane of the segment ends with the result. */
+/* Maximum of v over the T lanes of a segment (v >= -1, no NaN). */
 template <int T>
-__device__ __forceinline__ void segment_argmax(double &mag, int &key)
+__device__ __forceinline__ double segment_max(double v)
 {
-    if constexpr (T > 1) argmax_round<1>(mag, key);
-    if constexpr (T > 2) argmax_round<2>(mag, key);
-    if constexpr (T > 4) argmax_round<4>(mag, key);
-    if constexpr (T > 8) argmax_round<8>(mag, key);
-    if constexpr (T > 16) argmax_round<16>(mag, key);
+    if constexpr (T > 1) v = max_round<0>(v);
+    if constexpr (T > 2) v = max_round<1>(v);
+    if constexpr (T > 4) v = max_round<2>(v);
+    if constexpr (T > 8) v = max_round<3>(v);
+    if constexpr (T > 16) v = max_round<4>(v);
+    return v;
+}
+
+template <int T>
+__device__ __forceinline__ int segment_min(int v)
+{
+    if constexpr (T > 1) v = min_round<0>(v);
+    if constexpr (T > 2) v = min_round<1>(v);
+    if constexpr (T > 4) v = min_round<2>(v);
+    if constexpr (T > 8) v = min_round<3>(v);
+    if constexpr (T > 16) v = min_round<4>(v);
+    return v;
 }
 
 /* Factor (and solve, on info == 0) the system owned by this segment.
@@ -252,7 +266,14 @@ __device__ __forceinline__ void segment_argmax(double &mag, int &key)
  * pos[s] is the row's final position: the factors/solution entry held in
  * slot s belong to row pos[s] of the LAPACK-ordered result. seg_base is the
  * wave lane of the segment's lane 0. ipiv_k(k, v) is called by every lane
- * with the segment-uniform interchange ipiv[k] = v (1-based). */
+ * with the segment-uniform interchange ipiv[k] = v (1-based).
+ *
+ * Pivot search: the segment maximum of |a_rk| over candidate rows (pos >= k)
+ * is found with a VALU butterfly; a ballot of the lanes holding it gives the
+ * owner directly, and only when two lanes of some segment hold the same
+ * maximum (a tie, rare for non-integer data) does a second reduction pick
+ * the lowest position. The trailing update runs under the exec mask of the
+ * trailing rows (pos > k), with the pivot row broadcast beforehand. */
 template <int N, int T, typename IpivSink>
 __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N],
                                                  double (&b)[(N + T - 1) / T],
@@ -260,25 +281,44 @@ __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N]
                                                  IpivSink ipiv_k)
 {
     constexpr int K = lanes_shape<N, T>::K;
+    constexpr int CH = 8; /* pivot-row columns broadcast per chunk */
     const int lane_in_seg = (int)__lane_id() - seg_base;
+    const unsigned lowmask = T >= 32 ? 0xffffffffu : ((1u << T) - 1u);
     int info = 0;
     static_for<0, N>(LUPP_SF(kc) {
         constexpr int k = decltype(kc)::value;
         /* local candidate: largest |a_rk| among rows with pos >= k, lowest pos on ties */
         double mag = -1.0;
-        int key = 0x7fffffff;
+        int lpos = 0x7fffffff, ls = 0;
         static_for<0, K>(LUPP_SF(sc) {
             constexpr int s = decltype(sc)::value;
             const double v = fabs(a[s][k]);
-            const int kk = (pos[s] << 13) | (s << 5) | lane_in_seg;
-            const bool take = (pos[s] >= k) && ((v > mag) || (v == mag && kk < key));
+            const bool cand = pos[s] >= k;
+            const bool take = cand && ((v > mag) || (v == mag && pos[s] < lpos));
             mag = take ? v : mag;
-            key = take ? kk : key;
+            lpos = take ? pos[s] : lpos;
+            ls = take ? s : ls;
         });
-        segment_argmax<T>(mag, key);
-        const int tp = key & 31;        /* owning lane within the segment */
-        const int sp = (key >> 5) & 0xff; /* owning slot */
-        const int q = key >> 13;        /* current position of the pivot row */
+        const double M = segment_max<T>(mag);
+        const uint64_t hits = __ballot(mag == M);
+        const unsigned sb = (unsigned)(hits >> (unsigned)seg_base) & lowmask;
+        int tp = (int)__builtin_ctz(sb | (1u << 31));
+        if (__ballot(__builtin_popcount(sb) > 1) != 0) {
+            /* a tie between lanes in some segment: lowest position wins */
+            const int pmin = segment_min<T>(mag == M ? lpos : 0x7fffffff);
+            const uint64_t h2 = __ballot(mag == M && lpos == pmin);
+            tp = (int)__builtin_ctz(((unsigned)(h2 >> (unsigned)seg_base) & lowmask) | (1u << 31));
+        }
+        const int src = seg_base + tp;
+        const int ql = bcast_i32((lpos << 8) | ls, src);
+        const int q = ql >> 8;  /* current position of the pivot row */
+        const int sp = ql & 0xff; /* its slot in lane tp */
+        double sel = a[0][k];
+        static_for<1, K>(LUPP_SF(sc) {
+            constexpr int s = decltype(sc)::value;
+            sel = (sp == s) ? a[s][k] : sel;
+        });
+        const double pv = bcast_f64(sel, src);
         ipiv_k(k, q + 1);
 
         /* positions: the row at position k moves to q, the pivot row takes k */
@@ -288,40 +328,15 @@ __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N]
             const int ps = pos[s];
             pos[s] = (own && sp == s) ? k : ((ps == k) ? q : ps);
         });
-
-        /* pivot entry: select the slot on every lane, fetch it from lane tp */
-        const int src = seg_base + tp;
-        double sel = a[0][k];
-        static_for<1, K>(LUPP_SF(sc) {
-            constexpr int s = decltype(sc)::value;
-            sel = (sp == s) ? a[s][k] : sel;
-        });
-        const double pv = bcast_f64(sel, src);
-        const bool zero = (mag == 0.0);
+        const bool zero = (M == 0.0);
         info = (zero && info == 0) ? k + 1 : info;
 
         if (!zero) {
             double l[K];
             static_for<0, K>(LUPP_SF(sc) {
                 constexpr int s = decltype(sc)::value;
-                l[s] = 0.0;
-                if (pos[s] > k) {
-                    l[s] = a[s][k] / pv;
-                    a[s][k] = l[s];
-                }
-            });
-            static_for<k + 1, N>(LUPP_SF(jc) {
-                constexpr int j = decltype(jc)::value;
-                double us = a[0][j];
-                static_for<1, K>(LUPP_SF(sc) {
-                    constexpr int s = decltype(sc)::value;
-                    us = (sp == s) ? a[s][j] : us;
-                });
-                const double u = bcast_f64(us, src);
-                static_for<0, K>(LUPP_SF(sc) {
-                    constexpr int s = decltype(sc)::value;
-                    if (pos[s] > k) a[s][j] = a[s][j] - l[s] * u;
-                });
+                l[s] = a[s][k] / pv;
+                a[s][k] = pos[s] > k ? l[s] : a[s][k];
             });
             double ys = b[0];
             static_for<1, K>(LUPP_SF(sc) {
@@ -329,15 +344,40 @@ __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N]
                 ys = (sp == s) ? b[s] : ys;
             });
             const double y = bcast_f64(ys, src);
-            static_for<0, K>(LUPP_SF(sc) {
-                constexpr int s = decltype(sc)::value;
-                if (pos[s] > k) b[s] = b[s] - l[s] * y;
+            static_for<0, (N - k - 1 + CH - 1) / CH>(LUPP_SF(cc) {
+                constexpr int j0 = k + 1 + decltype(cc)::value * CH;
+                constexpr int j1 = (j0 + CH < N) ? j0 + CH : N;
+                double u[CH];
+                static_for<j0, j1>(LUPP_SF(jc) {
+                    constexpr int j = decltype(jc)::value;
+                    double us = a[0][j];
+                    static_for<1, K>(LUPP_SF(sc) {
+                        constexpr int s = decltype(sc)::value;
+                        us = (sp == s) ? a[s][j] : us;
+                    });
+                    u[j - j0] = bcast_f64(us, src);
+                });
+                static_for<0, K>(LUPP_SF(sc) {
+                    constexpr int s = decltype(sc)::value;
+                    if (pos[s] > k) {
+                        static_for<j0, j1>(LUPP_SF(jc) {
+                            constexpr int j = decltype(jc)::value;
+                            a[s][j] = a[s][j] - l[s] * u[j - j0];
+                        });
+                        if constexpr (decltype(cc)::value == 0) b[s] = b[s] - l[s] * y;
+                    }
+                });
             });
+            if constexpr (k + 1 >= N) {
+                static_for<0, K>(LUPP_SF(sc) {
+                    constexpr int s = decltype(sc)::value;
+                    if (pos[s] > k) b[s] = b[s] - l[s] * y;
+                });
+            }
         }
     });
     if (info == 0) {
         /* back substitution, column j descending: x_j lives in the row at position j */
-        const uint64_t segmask = ((1ull << T) - 1ull) << (unsigned)seg_base;
         static_for_down<0, N>(LUPP_SF(jc) {
             constexpr int j = decltype(jc)::value;
             bool mine = false;
@@ -350,8 +390,8 @@ __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N]
                 us = hit ? a[s][j] : us;
             });
             const double xl = bs / us;
-            const uint64_t owners = __ballot(mine) & segmask;
-            const int owner = (int)__builtin_ctzll(owners | (1ull << 63));
+            const unsigned ob = (unsigned)(__ballot(mine) >> (unsigned)seg_base) & lowmask;
+            const int owner = seg_base + (int)__builtin_ctz(ob | (1u << 31));
             const double x = bcast_f64(xl, owner);
             static_for<0, K>(LUPP_SF(sc) {
                 constexpr int s = decltype(sc)::value;

@@ -12,6 +12,7 @@ from __future__ import annotations
 import argparse
 import concurrent.futures as cf
 import hashlib
+import json
 import os
 import shutil
 import subprocess
@@ -94,6 +95,22 @@ def generate(gen: str) -> list[str]:
         body = " ".join(f"if (c < cap) out[c] = {w}; ++c;" for w in ws)
         lines.append(f"  if (n == {n}) {{ {body} }}")
     lines.append("  return c;\n}")
+    # autotuned defaults measured on gfx950
+    tuned = {}
+    tp = os.path.join(PKG, "dispatch_gfx950.json")
+    if os.path.exists(tp):
+        for e in json.load(open(tp)).get("entries", []):
+            tuned[(int(e["n"]), 0 if e["layout"] == "aos" else 1, int(e["bucket"]))] = e
+    lines.append("bool tuned_choice(int n, int layout, int bucket, int *v, int *l, int *w) {")
+    for (n, lay, bk), e in sorted(tuned.items()):
+        v = 1 if e["variant"] == "thread" else 2
+        if v == 1 and n not in THREAD_NS:
+            continue
+        if v == 2 and (n, int(e["lanes"])) not in LANES:
+            continue
+        lines.append(f"  if (n == {n} && layout == {lay} && bucket == {bk}) {{ *v = {v}; *l = {int(e['lanes'])}; "
+                     f"*w = {int(e['wpb'])}; return true; }}")
+    lines.append("  (void)n; (void)layout; (void)bucket; (void)v; (void)l; (void)w;\n  return false;\n}")
     lines.append("}  // namespace lupp")
     p = os.path.join(gen, "registry.hip")
     _write_if_changed(p, "\n".join(lines) + "\n")

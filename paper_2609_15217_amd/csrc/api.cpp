@@ -22,18 +22,20 @@ struct lupp_ctx {
     int forced_variant = LUPP_VARIANT_AUTO;
     int forced_lanes = 0;
     int forced_wpb = 0;
-    lupp::Choice table[33][2];
+    lupp::Choice table[33][2][2]; /* [n][layout][batch bucket] */
     void *ragged_ws = nullptr;   /* device workspace of the ragged path */
     size_t ragged_ws_bytes = 0;
 };
 
 namespace lupp {
 
-/* Defaults before autotuning: registers-only thread path while a system fits
- * one lane comfortably, then one row per lane. */
-static Choice default_choice(int n, int layout)
+/* Default dispatch: the table the autotuner measured on gfx950 (compiled in
+ * by the build from dispatch_gfx950.json), else registers-only thread path
+ * while a system fits one lane comfortably, then one row per lane. */
+static Choice default_choice(int n, int layout, int bucket)
 {
-    (void)layout;
+    int v = 0, l = 0, w = 0;
+    if (tuned_choice(n, layout, bucket, &v, &l, &w)) return {v, l, w};
     if (n <= 8) return {LUPP_VARIANT_THREAD, 1, 4};
     if (n <= 16) return {LUPP_VARIANT_LANES, 16, 4};
     return {LUPP_VARIANT_LANES, 32, 4};
@@ -43,14 +45,18 @@ static bool fits_offsets(int n, int64_t batch, int layout, int variant, int lane
                          int64_t sA, int64_t sB)
 {
     const int64_t lim = (int64_t)1 << 31;
+    (void)variant;
     if (layout == LUPP_SOA) {
-        if (variant == LUPP_VARIANT_THREAD) return true;
         (void)batch;
-        return ((int64_t)(n - 1) * sA + 64) * 8 < lim && ((int64_t)(n - 1) * sB + 64) * 8 < lim;
+        return ((int64_t)(n - 1) * sA + 256) * 8 < lim && ((int64_t)(n - 1) * sB + 256) * 8 < lim;
     }
     const int64_t per = variant == LUPP_VARIANT_THREAD ? 256 : 64 / (lanes > 0 ? lanes : 1);
     return per * sA * 8 < lim && per * sB * 8 < lim && per * n * 4 < lim;
 }
+
+/* Batch-size bucket of the dispatch table: small batches (latency-bound,
+ * the GPU is not filled) and large ones. */
+static int bucket_of(int64_t batch) { return batch < kSmallBatch ? 0 : 1; }
 
 static LaunchFn pick(int n, const Choice &c)
 {
@@ -77,7 +83,8 @@ int lupp_create(lupp_ctx **ctx, int device)
     if (c == nullptr) return LUPP_E_NOMEM;
     c->device = device;
     for (int n = 0; n <= 32; ++n)
-        for (int l = 0; l < 2; ++l) c->table[n][l] = default_choice(n < 1 ? 1 : n, l);
+        for (int l = 0; l < 2; ++l)
+            for (int bk = 0; bk < 2; ++bk) c->table[n][l][bk] = default_choice(n < 1 ? 1 : n, l, bk);
     *ctx = c;
     return 0;
 }
@@ -111,25 +118,29 @@ int lupp_force_variant(lupp_ctx *ctx, int variant, int lanes, int wpb)
     return 0;
 }
 
-int lupp_set_dispatch(lupp_ctx *ctx, int n, int layout, int variant, int lanes, int wpb)
+int lupp_set_dispatch(lupp_ctx *ctx, int n, int layout, int64_t batch, int variant, int lanes,
+                      int wpb)
 {
     if (ctx == nullptr) return -1;
     if (n < 1 || n > 32) return -2;
     if (layout != LUPP_AOS && layout != LUPP_SOA) return -3;
-    if (variant != LUPP_VARIANT_THREAD && variant != LUPP_VARIANT_LANES) return -4;
+    if (batch < 0) return -4;
+    if (variant != LUPP_VARIANT_THREAD && variant != LUPP_VARIANT_LANES) return -5;
     const Choice c{variant, lanes, wpb};
-    if (pick(n, c) == nullptr) return -5;
-    if (wpb != 0 && wpb != 1 && wpb != 2 && wpb != 4) return -6;
-    ctx->table[n][layout] = c;
+    if (pick(n, c) == nullptr) return -6;
+    if (wpb != 0 && wpb != 1 && wpb != 2 && wpb != 4) return -7;
+    ctx->table[n][layout][bucket_of(batch)] = c;
     return 0;
 }
 
-int lupp_get_dispatch(lupp_ctx *ctx, int n, int layout, int *variant, int *lanes, int *wpb)
+int lupp_get_dispatch(lupp_ctx *ctx, int n, int layout, int64_t batch, int *variant, int *lanes,
+                      int *wpb)
 {
     if (ctx == nullptr) return -1;
     if (n < 1 || n > 32) return -2;
     if (layout != LUPP_AOS && layout != LUPP_SOA) return -3;
-    const Choice &c = ctx->table[n][layout];
+    if (batch < 0) return -4;
+    const Choice &c = ctx->table[n][layout][bucket_of(batch)];
     if (variant) *variant = c.variant;
     if (lanes) *lanes = c.lanes;
     if (wpb) *wpb = c.wpb;
@@ -164,20 +175,13 @@ int lupp_batched_solve(lupp_ctx *ctx, int n, int64_t batch, int layout, double *
     if (bad != 0) return bad;
     if (batch == 0) return 0;
 
-    Choice c = ctx->table[n][layout];
+    Choice c = ctx->table[n][layout][bucket_of(batch)];
     if (ctx->forced_variant != LUPP_VARIANT_AUTO)
         c = Choice{ctx->forced_variant, ctx->forced_lanes, ctx->forced_wpb};
     LaunchFn fn = pick(n, c);
     if (fn == nullptr) return LUPP_E_UNSUPPORTED;
-    if (!fits_offsets(n, batch, layout, c.variant, c.lanes, strideA, strideB)) {
-        /* the thread path has no 32-bit offset limit in SoA */
-        const Choice t{LUPP_VARIANT_THREAD, 1, 4};
-        if (ctx->forced_variant != LUPP_VARIANT_AUTO || thread_launcher(n) == nullptr ||
-            !fits_offsets(n, batch, layout, t.variant, t.lanes, strideA, strideB))
-            return LUPP_E_UNSUPPORTED;
-        c = t;
-        fn = thread_launcher(n);
-    }
+    if (!fits_offsets(n, batch, layout, c.variant, c.lanes, strideA, strideB))
+        return LUPP_E_UNSUPPORTED;
     int cur = 0;
     hipGetDevice(&cur);
     if (cur != ctx->device) hipSetDevice(ctx->device);
@@ -207,6 +211,89 @@ int lupp_batched_solve_ragged(lupp_ctx *ctx, int64_t batch, const int32_t *n,
     if (cur != ctx->device) hipSetDevice(ctx->device);
     const int rc = ragged_launch(ctx, batch, n, offA, offB, A, b, ipiv, info,
                                  (flags & LUPP_KEEP_A) == 0, (hipStream_t)stream);
+    if (cur != ctx->device) hipSetDevice(cur);
+    return rc;
+}
+
+int lupp_autotune(lupp_ctx *ctx, int n, int64_t batch, int layout, const double *A, int64_t lda,
+                  int64_t strideA, const double *b, int64_t strideB, int reps, int *variant,
+                  int *lanes, int *wpb, float *ms, void *stream)
+{
+    if (ctx == nullptr) return -1;
+    const int bad = lupp_check_solve_args(n, batch, layout, A, lda, strideA, b, strideB,
+                                          (const int32_t *)1, (const int32_t *)1, 0);
+    if (bad != 0) return bad;
+    if (batch == 0) return -3;
+    if (reps < 1) return -10;
+    int cur = 0;
+    hipGetDevice(&cur);
+    if (cur != ctx->device) hipSetDevice(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t nA = layout == LUPP_AOS ? (size_t)batch * strideA : (size_t)n * lda * strideA;
+    const size_t nB = layout == LUPP_AOS ? (size_t)batch * strideB : (size_t)n * strideB;
+    const size_t nP = layout == LUPP_AOS ? (size_t)batch * n : (size_t)n * strideA;
+    double *wA = nullptr, *wB = nullptr;
+    int32_t *wP = nullptr, *wI = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = 0;
+    hipError_t e = hipMalloc(&wA, nA * 8);
+    if (e == hipSuccess) e = hipMalloc(&wB, nB * 8);
+    if (e == hipSuccess) e = hipMalloc(&wP, nP * 4);
+    if (e == hipSuccess) e = hipMalloc(&wI, (size_t)batch * 4);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? LUPP_E_NOMEM : hip_err(e);
+
+    Choice best{0, 0, 0};
+    float best_ms = 3.0e38f;
+    int widths[8];
+    const int nw = lanes_widths(n, widths, 8);
+    Choice cands[64];
+    int nc = 0;
+    for (int w = 1; w <= 4; w <<= 1) {
+        if (thread_launcher(n) != nullptr) cands[nc++] = {LUPP_VARIANT_THREAD, 1, w};
+        for (int i = 0; i < nw; ++i) cands[nc++] = {LUPP_VARIANT_LANES, widths[i], w};
+    }
+    SolveArgs a{batch, wA, lda, strideA, wB, strideB, wP, wI};
+    for (int c = 0; c < nc && rc == 0; ++c) {
+        if (!fits_offsets(n, batch, layout, cands[c].variant, cands[c].lanes, strideA, strideB))
+            continue;
+        LaunchFn fn = pick(n, cands[c]);
+        float t[64];
+        const int r_total = reps + 1 < 64 ? reps + 1 : 64;
+        for (int r = 0; r < r_total && rc == 0; ++r) {
+            e = hipMemcpyAsync(wA, A, nA * 8, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(wB, b, nB * 8, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            if (e == hipSuccess) e = fn(a, layout, true, cands[c].wpb, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t[r], e0, e1);
+            if (e != hipSuccess) rc = hip_err(e);
+        }
+        if (rc != 0) break;
+        /* median of the timed repetitions (the first launch is a warm-up) */
+        for (int i = 1; i < r_total; ++i)
+            for (int j = i + 1; j < r_total; ++j)
+                if (t[j] < t[i]) { float x = t[i]; t[i] = t[j]; t[j] = x; }
+        const float med = t[1 + (r_total - 1) / 2];
+        if (med < best_ms) { best_ms = med; best = cands[c]; }
+    }
+    if (rc == 0 && best.variant != 0) {
+        ctx->table[n][layout][bucket_of(batch)] = best;
+        if (variant) *variant = best.variant;
+        if (lanes) *lanes = best.lanes;
+        if (wpb) *wpb = best.wpb;
+        if (ms) *ms = best_ms;
+    } else if (rc == 0) {
+        rc = LUPP_E_UNSUPPORTED;
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(wA);
+    hipFree(wB);
+    hipFree(wP);
+    hipFree(wI);
     if (cur != ctx->device) hipSetDevice(cur);
     return rc;
 }

@@ -111,7 +111,7 @@ __device__ __forceinline__ void law_assemble(const LawK &P, const double (&de)[6
 template <int NU>
 __global__ void __launch_bounds__(256) k_newton(lupp_points pts, LawK P, double tol, int maxit)
 {
-    const int64_t p0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t p0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
     const int64_t rem = pts.count - p0;
     const uint32_t nvalid = (uint32_t)(rem < (int64_t)blockDim.x ? rem : blockDim.x);
     const uint32_t tid = threadIdx.x;

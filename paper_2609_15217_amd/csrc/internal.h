@@ -33,6 +33,11 @@ const void *thread_kernel_symbol(int n);
 const void *lanes_kernel_symbol(int n, int lanes);
 /* Segment widths compiled for size n (ascending), returns the count. */
 int lanes_widths(int n, int *out, int cap);
+/* Batches below this size use the small-batch dispatch entries. */
+constexpr int64_t kSmallBatch = 32768;
+/* Autotuned default for (n, layout, batch bucket), compiled in by the build;
+ * false if the table has no entry. */
+bool tuned_choice(int n, int layout, int bucket, int *variant, int *lanes, int *wpb);
 constexpr int kThreadMaxN = 13;
 
 /* Constitutive update launcher (constitutive.hip). */
@@ -90,6 +95,32 @@ __device__ __forceinline__ void buf_store_i32(__amdgpu_buffer_rsrc_t r, uint32_t
                                               uint32_t soff, int x)
 {
     __builtin_amdgcn_raw_buffer_store_b32(x, r, (int)voff, (int)soff, 0);
+}
+
+/* Workgroups are dispatched to the 8 XCDs round robin (workgroup b runs on
+ * XCD b % 8), and each XCD has its own L2. Remapping so that every XCD
+ * processes one contiguous range of logical workgroups keeps neighbouring
+ * systems - which share cache lines in the interleaved layout - in the same
+ * L2. The map is a bijection on [0, G). */
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G)
+{
+    constexpr uint32_t X = 8;
+    const uint32_t q = G / X, r = G % X, x = b % X, i = b / X;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
+/* Returns p unchanged, but hides its value from the optimiser. Buffer
+ * descriptors built from the result cannot be merged with descriptors built
+ * earlier from p, so the earlier ones die instead of being kept alive (in
+ * spilled SGPRs) across the whole solve. */
+template <typename T>
+__device__ __forceinline__ T *opaque_ptr(T *p)
+{
+    const uint64_t v = (uint64_t)p;
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return (T *)(((uint64_t)hi << 32) | lo);
 }
 
 inline int hip_err(hipError_t e) { return e == hipSuccess ? 0 : LUPP_E_HIP_BASE - (int)e; }

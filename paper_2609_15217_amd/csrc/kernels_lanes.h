@@ -30,16 +30,16 @@ __global__ void __launch_bounds__(256) k_lanes(SolveArgs a, int layout, int fact
     const int lane = (int)__lane_id();
     const int g = lane / T, t = lane % T;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t sys0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * SPW;
+    const int64_t sys0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave) * SPW;
     const int64_t rem = a.batch - sys0;
     const int nvalid = (int)(rem <= 0 ? 0 : (rem < SPW ? rem : SPW));
     const bool active = g < nvalid;
 
     /* uniform bases and extents, per-lane offsets of row r of segment g */
-    const double *baseA = a.A + (soa ? sys0 : sys0 * a.sA);
+    double *baseA = a.A + (soa ? sys0 : sys0 * a.sA);
     const int64_t colA = soa ? a.lda * a.sA : a.lda; /* elements between columns */
     const uint32_t bytesA = (uint32_t)((soa ? (int64_t)(N - 1) * a.sA + nvalid : (int64_t)nvalid * a.sA) * 8);
-    const double *baseB = a.b + (soa ? sys0 : sys0 * a.sB);
+    double *baseB = a.b + (soa ? sys0 : sys0 * a.sB);
     const uint32_t bytesB = (uint32_t)((soa ? (int64_t)(N - 1) * a.sB + nvalid : (int64_t)nvalid * a.sB) * 8);
     auto offA = [&](int r) { return (uint32_t)((soa ? (int64_t)r * a.sA + g : (int64_t)g * a.sA + r) * 8); };
     auto offB = [&](int r) { return (uint32_t)((soa ? (int64_t)r * a.sB + g : (int64_t)g * a.sB + r) * 8); };
@@ -81,6 +81,9 @@ __global__ void __launch_bounds__(256) k_lanes(SolveArgs a, int layout, int fact
         });
     });
 
+    baseA = opaque_ptr(baseA);
+    baseB = opaque_ptr(baseB);
+    const auto rBs = make_rsrc(baseB, bytesB);
     /* slot s holds row pos[s] of the LAPACK-ordered result */
     static_for<0, K>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
@@ -99,7 +102,7 @@ __global__ void __launch_bounds__(256) k_lanes(SolveArgs a, int layout, int fact
     static_for<0, K>([&](auto sc) __attribute__((always_inline)) {
         constexpr int s = decltype(sc)::value;
         const bool ok = active && pos[s] >= 0 && inf == 0;
-        buf_store_f64(rB, ok ? offB(pos[s]) : kOutOfRange, 0, x[s]);
+        buf_store_f64(rBs, ok ? offB(pos[s]) : kOutOfRange, 0, x[s]);
     });
     /* AoS ipiv[s*N + k]; SoA ipiv[k*ldbatch + s] */
     const auto rP = make_rsrc(a.ipiv + (soa ? sys0 : sys0 * N),

@@ -9,8 +9,8 @@
  *        contiguous bytes per element);
  *   AoS: base = A + s0*strideA, E = 1,       V = strideA (each lane walks its
  *        own matrix; the wave's accesses are served through L1/L2 lines).
- * The uniform part goes into the buffer descriptor, the per-lane part into
- * one VGPR shared by all elements.
+ * The uniform part goes into the buffer descriptor and its offset field,
+ * the per-lane part into one VGPR shared by all elements.
  */
 #ifndef LUPP_KERNELS_THREAD_H
 #define LUPP_KERNELS_THREAD_H
@@ -20,64 +20,95 @@
 
 namespace lupp {
 
+/* Occupancy target per size: the register-resident matrix takes 2*N*N VGPRs,
+ * so small systems leave room for several waves per SIMD to hide latency,
+ * while n >= 9 needs most of the 512-entry register file of one wave. */
 template <int N>
-__global__ void __launch_bounds__(256) k_thread(SolveArgs a, int layout, int factors)
+constexpr int thread_waves_per_eu() { return N <= 4 ? 4 : (N <= 8 ? 2 : 1); }
+
+template <int N>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(thread_waves_per_eu<N>())))
+    k_thread(SolveArgs a, int layout, int factors)
 {
     const bool soa = layout == LUPP_SOA;
-    const int64_t s0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t s0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
     const int64_t rem = a.batch - s0;
     const uint32_t nvalid = (uint32_t)(rem < (int64_t)blockDim.x ? rem : blockDim.x);
     const uint32_t tid = threadIdx.x;
+    const bool active = tid < nvalid;
 
-    const int64_t EA = soa ? a.sA : 1, EB = soa ? a.sB : 1;
-    const double *bA = a.A + (soa ? s0 : s0 * a.sA);
-    const double *bB = a.b + (soa ? s0 : s0 * a.sB);
-    /* bytes reachable from one element's base by the block's valid lanes */
-    const uint32_t nbA = soa ? nvalid * 8u : nvalid * (uint32_t)a.sA * 8u;
-    const uint32_t nbB = soa ? nvalid * 8u : nvalid * (uint32_t)a.sB * 8u;
-    const uint32_t voA = soa ? tid * 8u : tid * (uint32_t)a.sA * 8u;
-    const uint32_t voB = soa ? tid * 8u : tid * (uint32_t)a.sB * 8u;
+    /* Element (i, j) of this lane's system sits at
+     *   colbase_j + i*R + tid*V   (elements), colbase_j = base + j*C,
+     * SoA: base = A + s0, C = lda*ldbatch, R = ldbatch, V = 1;
+     * AoS: base = A + s0*strideA, C = lda, R = 1, V = strideA.
+     * One descriptor per column; the row offset i*R goes in the uniform
+     * offset field and the lane offset in the VGPR. Descriptor extents cover
+     * exactly the valid lanes' elements, and lanes past the batch get an
+     * out-of-range lane offset. */
+    double *bA = a.A + (soa ? s0 : s0 * a.sA);
+    double *bB = a.b + (soa ? s0 : s0 * a.sB);
+    const int64_t C = soa ? a.lda * a.sA : a.lda;
+    const uint32_t R8 = (uint32_t)((soa ? a.sA : 1) * 8);
+    const uint32_t RB8 = (uint32_t)((soa ? a.sB : 1) * 8);
+    const uint32_t nbA = soa ? (uint32_t)(((int64_t)(N - 1) * a.sA + nvalid) * 8) : nvalid * (uint32_t)a.sA * 8u;
+    const uint32_t nbB = soa ? (uint32_t)(((int64_t)(N - 1) * a.sB + nvalid) * 8) : nvalid * (uint32_t)a.sB * 8u;
+    const uint32_t voA = !active ? kOutOfRange : (soa ? tid * 8u : tid * (uint32_t)a.sA * 8u);
+    const uint32_t voB = !active ? kOutOfRange : (soa ? tid * 8u : tid * (uint32_t)a.sB * 8u);
 
     double m[N][N];
     double x[N];
     int piv[N];
     static_for<0, N>([&](auto jc) __attribute__((always_inline)) {
         constexpr int j = decltype(jc)::value;
+        const auto r = make_rsrc(bA + j * C, nbA);
         static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
             constexpr int i = decltype(ic)::value;
-            m[j][i] = buf_load_f64(make_rsrc(bA + (i + j * a.lda) * EA, nbA), voA, 0);
+            m[j][i] = buf_load_f64(r, voA, i * R8);
         });
     });
-    static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
-        constexpr int i = decltype(ic)::value;
-        x[i] = buf_load_f64(make_rsrc(bB + i * EB, nbB), voB, 0);
-    });
+    {
+        const auto r = make_rsrc(bB, nbB);
+        static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(ic)::value;
+            x[i] = buf_load_f64(r, voB, i * RB8);
+        });
+    }
 
     const int inf = thread_getrf_solve<N, true>(m, x, piv);
 
+    bA = opaque_ptr(bA);
+    bB = opaque_ptr(bB);
     if (factors) {
         static_for<0, N>([&](auto jc) __attribute__((always_inline)) {
             constexpr int j = decltype(jc)::value;
+            const auto r = make_rsrc(bA + j * C, nbA);
             static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
                 constexpr int i = decltype(ic)::value;
-                buf_store_f64(make_rsrc(bA + (i + j * a.lda) * EA, nbA), voA, 0, m[j][i]);
+                buf_store_f64(r, voA, i * R8, m[j][i]);
             });
         });
     }
-    const uint32_t vx = inf == 0 ? voB : kOutOfRange;
-    static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
-        constexpr int i = decltype(ic)::value;
-        buf_store_f64(make_rsrc(bB + i * EB, nbB), vx, 0, x[i]);
-    });
+    {
+        const auto r = make_rsrc(bB, nbB);
+        const uint32_t vx = inf == 0 ? voB : kOutOfRange;
+        static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(ic)::value;
+            buf_store_f64(r, vx, i * RB8, x[i]);
+        });
+    }
     /* AoS ipiv[s*N + k]; SoA ipiv[k*ldbatch + s] */
-    const int32_t *bP = a.ipiv + (soa ? s0 : s0 * N);
-    const int64_t EP = soa ? a.sA : 1;
-    const uint32_t nbP = soa ? nvalid * 4u : nvalid * N * 4u;
-    const uint32_t voP = soa ? tid * 4u : tid * N * 4u;
-    static_for<0, N>([&](auto kc) __attribute__((always_inline)) {
-        constexpr int k = decltype(kc)::value;
-        buf_store_i32(make_rsrc(bP + k * EP, nbP), voP, 0, piv[k]);
-    });
+    {
+        int32_t *bP = opaque_ptr(a.ipiv + (soa ? s0 : s0 * N));
+        const uint32_t nbP = soa ? (uint32_t)(((int64_t)(N - 1) * a.sA + nvalid) * 4) : nvalid * N * 4u;
+        const uint32_t voP = !active ? kOutOfRange : (soa ? tid * 4u : tid * N * 4u);
+        const uint32_t RP4 = (uint32_t)((soa ? a.sA : 1) * 4);
+        const auto r = make_rsrc(bP, nbP);
+        static_for<0, N>([&](auto kc) __attribute__((always_inline)) {
+            constexpr int k = decltype(kc)::value;
+            buf_store_i32(r, voP, k * RP4, piv[k]);
+        });
+    }
     buf_store_i32(make_rsrc(a.info + s0, nvalid * 4u), tid * 4u, 0, inf);
 }
 

@@ -68,9 +68,10 @@ _lupp_batched_solve_ragged = _sig("lupp_batched_solve_ragged", ctypes.c_int,
 _lupp_force_variant = _sig("lupp_force_variant", ctypes.c_int,
                            [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int])
 _lupp_set_dispatch = _sig("lupp_set_dispatch", ctypes.c_int,
-                          [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int])
+                          [_P, ctypes.c_int, ctypes.c_int, _i64, ctypes.c_int, ctypes.c_int,
+                           ctypes.c_int])
 _lupp_get_dispatch = _sig("lupp_get_dispatch", ctypes.c_int,
-                          [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                          [_P, ctypes.c_int, ctypes.c_int, _i64, ctypes.POINTER(ctypes.c_int),
                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)])
 _lupp_variant_info = _sig("lupp_variant_info", ctypes.c_int,
                           [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -79,13 +80,18 @@ _constitutive_update = _sig("constitutive_update", ctypes.c_int,
                             [_P, ctypes.POINTER(lupp_points), ctypes.POINTER(lupp_law),
                              ctypes.c_double, ctypes.c_int, _P])
 _lupp_error_string = _sig("lupp_error_string", ctypes.c_char_p, [ctypes.c_int])
+_lupp_autotune = _sig("lupp_autotune", ctypes.c_int,
+                      [_P, ctypes.c_int, _i64, ctypes.c_int, _P, _i64, _i64, _P, _i64, ctypes.c_int,
+                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float), _P])
 _lupp_check_solve_args = _sig("lupp_check_solve_args", ctypes.c_int,
                               [ctypes.c_int, _i64, ctypes.c_int, _P, _i64, _i64, _P, _i64, _P, _P,
                                ctypes.c_uint])
 
 EXPORTED = ["lupp_create", "lupp_destroy", "lupp_batched_solve", "lupp_batched_solve_ragged",
             "lupp_force_variant", "lupp_set_dispatch", "lupp_get_dispatch", "lupp_variant_info",
-            "constitutive_update", "lupp_error_string", "lupp_check_solve_args"]
+            "constitutive_update", "lupp_error_string", "lupp_check_solve_args",
+            "lupp_autotune"]
 
 
 class LuppError(RuntimeError):
@@ -170,17 +176,28 @@ def lupp_check_solve_args(n: int, batch: int, layout: int, A, lda: int, strideA:
                                   _ptr(ipiv), _ptr(info), flags)
 
 
+def lupp_autotune(ctx: Context, n: int, batch: int, layout: int, A, lda: int, strideA: int, b,
+                  strideB: int, reps: int = 5, stream=None):
+    """Returns (rc, variant, lanes, wpb, ms)."""
+    v, l, w, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    rc = _lupp_autotune(ctx.handle, n, batch, layout, _ptr(A), lda, strideA, _ptr(b), strideB, reps,
+                        ctypes.byref(v), ctypes.byref(l), ctypes.byref(w), ctypes.byref(ms),
+                        _stream(stream))
+    return rc, v.value, l.value, w.value, ms.value
+
+
 def lupp_force_variant(ctx: Context, variant: int, lanes: int = 0, wpb: int = 0) -> int:
     return _lupp_force_variant(ctx.handle, variant, lanes, wpb)
 
 
-def lupp_set_dispatch(ctx: Context, n: int, layout: int, variant: int, lanes: int, wpb: int) -> int:
-    return _lupp_set_dispatch(ctx.handle, n, layout, variant, lanes, wpb)
+def lupp_set_dispatch(ctx: Context, n: int, layout: int, batch: int, variant: int, lanes: int,
+                      wpb: int) -> int:
+    return _lupp_set_dispatch(ctx.handle, n, layout, batch, variant, lanes, wpb)
 
 
-def lupp_get_dispatch(ctx: Context, n: int, layout: int):
+def lupp_get_dispatch(ctx: Context, n: int, layout: int, batch: int = 1 << 20):
     v, l, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    _check(_lupp_get_dispatch(ctx.handle, n, layout, ctypes.byref(v), ctypes.byref(l),
+    _check(_lupp_get_dispatch(ctx.handle, n, layout, batch, ctypes.byref(v), ctypes.byref(l),
                               ctypes.byref(w)), "lupp_get_dispatch")
     return v.value, l.value, w.value
 

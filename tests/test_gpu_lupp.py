@@ -194,7 +194,7 @@ def test_invalid_arguments(L, ctx):
     assert L.lupp_batched_solve(ctx, 8, 1, 0, t, 7, 64, t, 8, ti, ti) == -6
     assert L.lupp_batched_solve(ctx, 8, 1, 0, t, 8, 64, t, 8, ti, ti, flags=8) == -12
     assert L.lupp_force_variant(ctx, 2, 3, 0) == -3
-    assert L.lupp_set_dispatch(ctx, 20, 0, 1, 0, 0) == -5  # no thread kernel for n = 20
+    assert L.lupp_set_dispatch(ctx, 20, 0, 1 << 20, 1, 0, 0) == -6  # no thread kernel for n = 20
 
 
 def test_repeat_is_deterministic(L, ctx):

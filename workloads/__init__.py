@@ -8,6 +8,7 @@ decides which random matrices are kept.
 from .gen import (  # noqa: F401
     CHUNK,
     aos_to_soa,
+    device_systems,
     mixed_systems,
     newton_points,
     serving_requests,

@@ -123,6 +123,19 @@ def mixed_systems(batch: int, seed: int, nmin: int = 2, nmax: int = 32,
     return {"n": ns, "offA": offA, "offB": offB, "A": A, "b": b, "x_true": x}
 
 
+def device_systems(n: int, batch: int, seed: int, device="cuda"):
+    """Timing inputs drawn on the device with torch's seeded generator:
+    A ~ N(0,1) (batch, n, n) read [s][j][i], b ~ N(0,1) (batch, n). No
+    condition filter: pivoting statistics are those of the benchmark
+    distribution, which is what launch-configuration timing needs."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    A = torch.randn((batch, n, n), generator=g, dtype=torch.float64, device=device)
+    b = torch.randn((batch, n), generator=g, dtype=torch.float64, device=device)
+    return A, b
+
+
 def aos_to_soa(a: np.ndarray) -> np.ndarray:
     """(batch, n, n) -> (n, n, batch), or (batch, n) -> (n, batch)."""
     return np.ascontiguousarray(np.moveaxis(a, 0, -1))
