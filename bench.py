@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-newton", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--only", default=None, help="n:layout, e.g. 32:soa")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true")
@@ -228,6 +229,58 @@ def main():
                 "traffic": load_traffic(dom_key), "kernel": dom_key,
                 "algorithmic_bytes_per_launch": bytes_per_system(dom["n"]) * BATCH}
 
+    # ------------------------------------------------------------- ragged
+    ragged = {}
+    if not args.no_ragged:
+        # free the sweep buffers first
+        pristine.clear()
+        work.clear()
+        torch.cuda.empty_cache()
+        from workloads import mixed_systems
+        t1 = time.time()
+        mx = mixed_systems(2_000_000, seed=3)
+        log(f"mixed batch generated in {time.time() - t1:.1f}s")
+        nb = int(mx["n"].size)
+        tn = torch.from_numpy(mx["n"]).to(dev)
+        toA = torch.from_numpy(mx["offA"]).to(dev)
+        toB = torch.from_numpy(mx["offB"]).to(dev)
+        pA = torch.from_numpy(mx["A"]).to(dev)
+        pb = torch.from_numpy(mx["b"]).to(dev)
+        wA, wb = torch.empty_like(pA), torch.empty_like(pb)
+        rip = torch.empty(pb.numel(), dtype=torch.int32, device=dev)
+        rin = torch.empty(nb, dtype=torch.int32, device=dev)
+        n64 = mx["n"].astype(np.int64)
+        alg_bytes = int((16 * n64 * n64 + 20 * n64 + 4).sum()) + nb * (4 + 16)
+        alg_flops = int(sum(flops_per_system(n) * int((mx["n"] == n).sum()) for n in range(2, 33)))
+        for mode, flags in (("persistent", 0), ("per_size", L.LUPP_RAGGED_PER_SIZE)):
+            times = []
+            for r in range(args.warmup + args.steps):
+                wA.copy_(pA)
+                wb.copy_(pb)
+                torch.cuda.synchronize()
+                t_s = time.perf_counter()
+                rc = L.lupp_batched_solve_ragged(ctx, nb, tn, toA, toB, wA, wb, rip, rin, flags, stream)
+                torch.cuda.synchronize()
+                if rc != 0:
+                    raise RuntimeError(f"ragged {mode}: {L.lupp_error_string(rc)}")
+                if r >= args.warmup:
+                    times.append(time.perf_counter() - t_s)
+            if int((rin != 0).sum().item()):
+                raise RuntimeError(f"ragged {mode}: systems with info != 0")
+            sec = float(np.median(times))
+            ragged[mode] = {"ms": round(sec * 1e3, 3), "systems_per_s": round(nb / sec),
+                            "GBps": round(alg_bytes / sec / 1e9, 1),
+                            "hbm_frac": round(alg_bytes / sec / 1e9 / HBM_PEAK_GBS, 4),
+                            "fp64_TFLOPs": round(alg_flops / sec / 1e12, 3)}
+            log(f"ragged {mode}: {sec * 1e3:.2f} ms")
+        ragged["workload"] = ("2,000,000 FP64 systems, n ~ U{2..32}, A ~ N(0,1) rejected if "
+                              "cond2 > 1e4, AoS packed with int64 offsets, seed 3")
+        ragged["algorithmic_bytes"] = alg_bytes
+        ragged["speedup_persistent_vs_per_size"] = round(
+            ragged["per_size"]["ms"] / ragged["persistent"]["ms"], 3)
+        del tn, toA, toB, pA, pb, wA, wb, rip, rin, mx
+        torch.cuda.empty_cache()
+
     # ------------------------------------------------------------- latency
     lat = {}
     A1, b1, _ = systems(8, 4096, seed=1)
@@ -327,6 +380,7 @@ def main():
                    "mode": "strict (bitwise-reproducible, no FMA, true division)"},
         "roofline": roofline,
         "newton": newton,
+        "ragged": ragged,
         "latency": lat,
         "per_kernel": per_kernel,
         "cpu_baseline": cpu,

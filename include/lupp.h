@@ -46,8 +46,12 @@ extern "C" {
 #define LUPP_AOS 0
 #define LUPP_SOA 1
 
-/* Flags. LUPP_KEEP_A: do not write the factors back (A is left unchanged). */
+/* Flags. LUPP_KEEP_A: do not write the factors back (A is left unchanged).
+ * LUPP_RAGGED_PER_SIZE (lupp_batched_solve_ragged only): instead of the one
+ * persistent launch, read the size histogram back to the host and launch one
+ * kernel per size (the plain baseline; it synchronises the stream). */
 #define LUPP_KEEP_A 1u
+#define LUPP_RAGGED_PER_SIZE 2u
 
 /* Kernel variants (for lupp_force_variant and lupp_variant_info). */
 #define LUPP_VARIANT_AUTO 0
@@ -102,8 +106,12 @@ int lupp_check_solve_args(int n, int64_t batch, int layout, const double *A, int
  * size n[s] in 1..32, its matrix column-major at A + offA[s] with lda = n[s],
  * its right-hand side at b + offB[s] and its pivots at ipiv + offB[s].
  * Systems must not overlap. n, offA, offB are device arrays of `batch`
- * entries. The library groups systems by size on the device (workspace owned
- * by the context) and serves every group from one persistent kernel launch. */
+ * (<= 2^31 - 1) entries. The library groups systems by size on the device
+ * (histogram, plan, scatter; workspace owned by the context, grown with
+ * hipMalloc when a larger batch arrives) and serves every size from one
+ * persistent kernel launch, largest sizes first. A system whose n is outside
+ * 1..32 gets info = -1 and is not touched. flags: LUPP_KEEP_A,
+ * LUPP_RAGGED_PER_SIZE. */
 int lupp_batched_solve_ragged(lupp_ctx *ctx, int64_t batch, const int32_t *n,
                               const int64_t *offA, const int64_t *offB, double *A, double *b,
                               int32_t *ipiv, int32_t *info, unsigned flags, void *stream);

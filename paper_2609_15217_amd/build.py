@@ -71,8 +71,19 @@ def generate(gen: str) -> list[str]:
         p = os.path.join(gen, f"lanes_{n}_{t}.hip")
         _write_if_changed(p, f'#include "kernels_lanes.h"\nLUPP_LANES_INSTANCE({n}, {t})\n')
         srcs.append(p)
+    for g in range(4):
+        ns = [n for n in range(1, 33) if (n - 1) % 4 == g]
+        p = os.path.join(gen, f"ragged_one_{g}.hip")
+        _write_if_changed(p, '#include "kernels_ragged.h"\n' +
+                          "".join(f"LUPP_RAGGED_ONE_INSTANCE({n})\n" for n in ns))
+        srcs.append(p)
     # registry
-    lines = ['#include "internal.h"', "namespace lupp {"]
+    lines = ['#include "internal.h"', '#include "kernels_ragged.h"', "namespace lupp {"]
+    for n in range(1, 33):
+        lines.append(f"hipError_t ragged_one_launch_{n}(const RaggedArgs &, int, hipStream_t);")
+    lines.append("hipError_t ragged_one_launch(int n, const RaggedArgs &a, int items, hipStream_t st) {\n  switch (n) {")
+    lines += [f"  case {n}: return ragged_one_launch_{n}(a, items, st);" for n in range(1, 33)]
+    lines.append("  default: return hipErrorInvalidValue;\n  }\n}")
     for n in THREAD_NS:
         lines.append(f"LaunchFn thread_fn_{n}(); const void *thread_sym_{n}();")
     for n, t in LANES:
@@ -191,6 +202,8 @@ def _weight(src: str) -> int:
     if b.startswith("thread_"):
         n = int(b[7:-4])
         return 4 * n ** 3
+    if b.startswith("ragged"):
+        return 200_000
     return 50_000 if "constitutive" in b else 0
 
 

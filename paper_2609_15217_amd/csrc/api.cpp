@@ -23,8 +23,7 @@ struct lupp_ctx {
     int forced_lanes = 0;
     int forced_wpb = 0;
     lupp::Choice table[33][2][2]; /* [n][layout][batch bucket] */
-    void *ragged_ws = nullptr;   /* device workspace of the ragged path */
-    size_t ragged_ws_bytes = 0;
+    lupp::RaggedWs *ragged_ws = nullptr; /* device workspace of the ragged path */
 };
 
 namespace lupp {
@@ -96,7 +95,7 @@ void lupp_destroy(lupp_ctx *ctx)
         int cur = 0;
         hipGetDevice(&cur);
         hipSetDevice(ctx->device);
-        hipFree(ctx->ragged_ws);
+        ragged_ws_destroy(ctx->ragged_ws);
         hipSetDevice(cur);
     }
     delete ctx;
@@ -204,13 +203,15 @@ int lupp_batched_solve_ragged(lupp_ctx *ctx, int64_t batch, const int32_t *n,
     if (batch > 0 && b == nullptr) return -7;
     if (batch > 0 && ipiv == nullptr) return -8;
     if (batch > 0 && info == nullptr) return -9;
-    if ((flags & ~LUPP_KEEP_A) != 0) return -10;
+    if ((flags & ~(LUPP_KEEP_A | LUPP_RAGGED_PER_SIZE)) != 0) return -10;
     if (batch == 0) return 0;
     int cur = 0;
     hipGetDevice(&cur);
     if (cur != ctx->device) hipSetDevice(ctx->device);
-    const int rc = ragged_launch(ctx, batch, n, offA, offB, A, b, ipiv, info,
-                                 (flags & LUPP_KEEP_A) == 0, (hipStream_t)stream);
+    if (ctx->ragged_ws == nullptr) ctx->ragged_ws = ragged_ws_create();
+    const int rc = ragged_launch_impl(ctx->ragged_ws, batch, n, offA, offB, A, b, ipiv, info,
+                                      (flags & LUPP_KEEP_A) == 0,
+                                      (flags & LUPP_RAGGED_PER_SIZE) != 0, (hipStream_t)stream);
     if (cur != ctx->device) hipSetDevice(cur);
     return rc;
 }

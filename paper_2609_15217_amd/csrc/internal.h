@@ -45,11 +45,13 @@ int constitutive_launch(const lupp_points *pts, const lupp_law *law, double tol,
                         hipStream_t stream);
 const void *constitutive_kernel_symbol(int kind);
 
-/* Ragged batch (ragged.hip). */
-struct lupp_ragged_ws;
-int ragged_launch(lupp_ctx *ctx, int64_t batch, const int32_t *n, const int64_t *offA,
-                  const int64_t *offB, double *A, double *b, int32_t *ipiv, int32_t *info,
-                  bool factors, hipStream_t stream);
+/* Ragged batch (ragged.hip): device workspace owned by a context. */
+struct RaggedWs;
+RaggedWs *ragged_ws_create();
+void ragged_ws_destroy(RaggedWs *ws);
+int ragged_launch_impl(RaggedWs *ws, int64_t batch, const int32_t *n, const int64_t *offA,
+                       const int64_t *offB, double *A, double *b, int32_t *ipiv, int32_t *info,
+                       bool factors, bool per_size, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Device-side memory access through buffer resources.                      */

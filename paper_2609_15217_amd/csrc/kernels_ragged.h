@@ -1,0 +1,204 @@
+/* Mixed-size (ragged) batches (Section 4.1: a size-aware dispatcher picks the
+ * specialised solver for each problem size).
+ *
+ * Systems are grouped by size on the device: a histogram, a plan that lays
+ * the size bins out in descending n (costliest work first) and cuts each bin
+ * into work items, and a scatter of system indices into the bins. The solve
+ * is then either one persistent launch whose workgroups pull work items from
+ * an atomic counter and dispatch on n, or one launch per size.
+ *
+ * System s: matrix column-major at A + offA[s] (lda = n[s]), right-hand side
+ * and pivots at offset offB[s], info[s].
+ */
+#ifndef LUPP_KERNELS_RAGGED_H
+#define LUPP_KERNELS_RAGGED_H
+
+#include "internal.h"
+#include "lupp_device.h"
+
+namespace lupp {
+
+constexpr int kRaggedWaves = 4;       /* wave64s per workgroup */
+constexpr int kRaggedThreads = 64 * kRaggedWaves;
+
+struct RaggedPlan {
+    int32_t count[33];      /* systems of each size */
+    int32_t bin_start[33];  /* first index of each size in `sorted` */
+    int32_t cursor[33];     /* scatter cursors */
+    int32_t item_start[33]; /* first work item of each size */
+    int32_t total_items;
+    int32_t next_item;      /* persistent-launch work counter */
+    int32_t bad;            /* systems with n outside 1..32 */
+};
+
+struct RaggedArgs {
+    int64_t batch;
+    const int32_t *n;
+    const int64_t *offA, *offB;
+    double *A, *b;
+    int32_t *ipiv, *info;
+    int factors;
+    int32_t *sorted;
+    RaggedPlan *plan;
+};
+
+/* Per-size solver used inside the ragged kernels: thread path for n <= 5,
+ * T-lane segments above; every choice stays within about 128 VGPRs so the
+ * persistent kernel (which holds all sizes) keeps 4 waves per SIMD. */
+__host__ __device__ constexpr int ragged_lanes(int n)
+{
+    return n <= 5 ? 1 : (n <= 16 ? 8 : 32);
+}
+
+/* systems one workgroup solves at once for size n */
+__host__ __device__ constexpr int ragged_per_round(int n)
+{
+    return ragged_lanes(n) == 1 ? kRaggedThreads : kRaggedWaves * (64 / ragged_lanes(n));
+}
+
+/* rounds per work item: items large enough to amortise taking one from the
+ * queue, small enough to balance the load across the GPU */
+constexpr int kRaggedRounds = 4;
+
+/* systems handled by one workgroup for one work item */
+__host__ __device__ constexpr int ragged_per_item(int n)
+{
+    return kRaggedRounds * ragged_per_round(n);
+}
+
+template <int N>
+__device__ __forceinline__ void ragged_item(const RaggedArgs &a, int first, int cnt)
+{
+    constexpr int T = ragged_lanes(N);
+    const int32_t *idx = a.sorted + a.plan->bin_start[N] + first;
+    if constexpr (T == 1) {
+        const int i = threadIdx.x;
+        const bool act = i < cnt;
+        const int64_t s = act ? idx[i] : 0;
+        const double *pA = a.A + (act ? a.offA[s] : 0);
+        const double *pB = a.b + (act ? a.offB[s] : 0);
+        double m[N][N], x[N];
+        int piv[N];
+        static_for<0, N>([&](auto jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(jc)::value;
+            static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
+                constexpr int ii = decltype(ic)::value;
+                m[j][ii] = act ? pA[ii + j * N] : 0.0;
+            });
+            x[j] = act ? pB[j] : 0.0;
+        });
+        const int inf = thread_getrf_solve<N, true>(m, x, piv);
+        if (act) {
+            double *wA = a.A + a.offA[s];
+            double *wB = a.b + a.offB[s];
+            int32_t *wP = a.ipiv + a.offB[s];
+            if (a.factors) {
+                static_for<0, N>([&](auto jc) __attribute__((always_inline)) {
+                    constexpr int j = decltype(jc)::value;
+                    static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
+                        constexpr int ii = decltype(ic)::value;
+                        wA[ii + j * N] = m[j][ii];
+                    });
+                });
+            }
+            static_for<0, N>([&](auto kc) __attribute__((always_inline)) {
+                constexpr int k = decltype(kc)::value;
+                wP[k] = piv[k];
+                if (inf == 0) wB[k] = x[k];
+            });
+            a.info[s] = inf;
+        }
+    } else {
+        constexpr int K = lanes_shape<N, T>::K;
+        constexpr int SPW = 64 / T;
+        const int lane = (int)__lane_id();
+        const int g = lane / T, t = lane % T;
+        const int wave = threadIdx.x >> 6;
+        const int j0 = wave * SPW + g;
+        const bool act = j0 < cnt;
+        const int64_t s = act ? idx[j0] : 0;
+        const double *pA = a.A + (act ? a.offA[s] : 0);
+        const double *pB = a.b + (act ? a.offB[s] : 0);
+        double m[K][N], x[K];
+        int pos[K];
+        static_for<0, K>([&](auto sc) __attribute__((always_inline)) {
+            constexpr int sl = decltype(sc)::value;
+            const int r = t + sl * T;
+            const bool ok = act && r < N;
+            pos[sl] = r < N ? r : -1;
+            static_for<0, N>([&](auto jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(jc)::value;
+                m[sl][j] = ok ? pA[r + j * N] : 0.0;
+            });
+            x[sl] = ok ? pB[r] : 0.0;
+        });
+        constexpr int KP = (N + T - 1) / T;
+        int pv[KP];
+        static_for<0, KP>([&](auto sc) __attribute__((always_inline)) { pv[decltype(sc)::value] = 0; });
+        const int inf = lanes_getrf_solve<N, T>(m, x, pos, g * T, [&](int k, int v) {
+            const int c = k / T;
+            static_for<0, KP>([&](auto sc) __attribute__((always_inline)) {
+                constexpr int cc = decltype(sc)::value;
+                if (cc == c) pv[cc] = (t == k % T) ? v : pv[cc];
+            });
+        });
+        if (act) {
+            double *wA = a.A + a.offA[s];
+            double *wB = a.b + a.offB[s];
+            int32_t *wP = a.ipiv + a.offB[s];
+            static_for<0, K>([&](auto sc) __attribute__((always_inline)) {
+                constexpr int sl = decltype(sc)::value;
+                if (pos[sl] >= 0) {
+                    if (a.factors) {
+                        static_for<0, N>([&](auto jc) __attribute__((always_inline)) {
+                            constexpr int j = decltype(jc)::value;
+                            wA[pos[sl] + j * N] = m[sl][j];
+                        });
+                    }
+                    if (inf == 0) wB[pos[sl]] = x[sl];
+                }
+            });
+            static_for<0, KP>([&](auto sc) __attribute__((always_inline)) {
+                constexpr int c = decltype(sc)::value;
+                if (t + c * T < N) wP[t + c * T] = pv[c];
+            });
+            if (t == 0) a.info[s] = inf;
+        }
+    }
+}
+
+/* Solve the work item `it` of size N (all threads of the workgroup). */
+template <int N>
+__device__ __forceinline__ void ragged_run_item(const RaggedArgs &a, int it)
+{
+    const int local = it - a.plan->item_start[N];
+    const int first = local * ragged_per_item(N);
+    for (int r = 0; r < kRaggedRounds; ++r) {
+        const int f = first + r * ragged_per_round(N);
+        const int rest = a.plan->count[N] - f;
+        if (rest <= 0) break;
+        ragged_item<N>(a, f, rest < ragged_per_round(N) ? rest : ragged_per_round(N));
+    }
+}
+
+/* One size per launch: workgroup b solves work item b of size N. */
+template <int N>
+__global__ void __launch_bounds__(kRaggedThreads) k_ragged_one(RaggedArgs a)
+{
+    const int it = a.plan->item_start[N] + (int)blockIdx.x;
+    ragged_run_item<N>(a, it);
+}
+
+}  // namespace lupp
+
+#define LUPP_RAGGED_ONE_INSTANCE(N)                                                 \
+    namespace lupp {                                                               \
+    hipError_t ragged_one_launch_##N(const RaggedArgs &a, int items, hipStream_t st)   \
+    {                                                                              \
+        if (items <= 0) return hipSuccess;                                         \
+        hipLaunchKernelGGL((k_ragged_one<N>), dim3((unsigned)items), dim3(kRaggedThreads), 0, st, a); \
+        return hipGetLastError();                                                  \
+    }                                                                              \
+    }
+
+#endif

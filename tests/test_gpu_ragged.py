@@ -1,0 +1,112 @@
+"""GPU parity of mixed-size (ragged) batches against the CPU oracle.
+
+Both schedules (one persistent launch over all sizes, and one launch per
+size) must reproduce the oracle's pivots, info, factors and solutions bit for
+bit, whatever the mix of sizes.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import mixed_systems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2609_15217_amd.lupp as L
+    return L
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    return L.Context(0)
+
+
+def run(L, ctx, mx, flags=0):
+    dev = torch.device("cuda:0")
+    batch = mx["n"].size
+    t = {k: torch.from_numpy(np.ascontiguousarray(mx[k])).to(dev) for k in ("n", "offA", "offB", "A", "b")}
+    ipiv = torch.full((mx["b"].size,), -9, dtype=torch.int32, device=dev)
+    info = torch.full((batch,), -7, dtype=torch.int32, device=dev)
+    rc = L.lupp_batched_solve_ragged(ctx, batch, t["n"], t["offA"], t["offB"], t["A"], t["b"], ipiv,
+                                     info, flags)
+    assert rc == 0, L.lupp_error_string(rc)
+    torch.cuda.synchronize()
+    return {"LU": t["A"].cpu().numpy(), "x": t["b"].cpu().numpy(), "ipiv": ipiv.cpu().numpy(),
+            "info": info.cpu().numpy()}
+
+
+def same(ref, got, keep_a=False, A=None):
+    assert np.array_equal(got["info"], ref["info"])
+    assert np.array_equal(got["ipiv"], ref["ipiv"])
+    assert np.array_equal(got["LU"], A if keep_a else ref["LU"])
+    assert np.array_equal(got["x"], ref["x"])
+
+
+@pytest.mark.parametrize("flags", [0, 2])
+@pytest.mark.parametrize("batch,nmin,nmax", [(3001, 2, 32), (777, 1, 8), (1500, 17, 32), (1, 32, 32),
+                                             (600, 13, 13)])
+def test_mixed_sizes_bitwise(L, ctx, batch, nmin, nmax, flags):
+    mx = mixed_systems(batch, seed=300 + batch, nmin=nmin, nmax=nmax, kappa_max=None)
+    ref = oracle.gesv_ragged(mx["n"], mx["offA"], mx["offB"], mx["A"], mx["b"], threads=8)
+    same(ref, run(L, ctx, mx, flags))
+
+
+def test_keep_a_and_repeat(L, ctx):
+    mx = mixed_systems(2000, seed=31, kappa_max=None)
+    ref = oracle.gesv_ragged(mx["n"], mx["offA"], mx["offB"], mx["A"], mx["b"], threads=8)
+    g1 = run(L, ctx, mx, L.LUPP_KEEP_A)
+    same(ref, g1, keep_a=True, A=mx["A"])
+    g2 = run(L, ctx, mx, L.LUPP_KEEP_A)
+    for k in g1:
+        assert np.array_equal(g1[k], g2[k])
+
+
+def test_singular_and_invalid_sizes(L, ctx):
+    mx = mixed_systems(400, seed=32, kappa_max=None)
+    # make a few systems exactly singular (zero first column)
+    for s in (3, 50, 399):
+        n = int(mx["n"][s])
+        o = int(mx["offA"][s])
+        mx["A"][o:o + n] = 0.0
+    ref = oracle.gesv_ragged(mx["n"], mx["offA"], mx["offB"], mx["A"], mx["b"], threads=4)
+    assert ref["info"][3] == 1 and ref["info"][50] == 1
+    same(ref, run(L, ctx, mx))
+    # sizes outside 1..32 are reported with info = -1 and left alone
+    bad = {k: v.copy() for k, v in mx.items()}
+    bad["n"][7] = 0
+    bad["n"][8] = 33
+    got = run(L, ctx, bad)
+    assert got["info"][7] == -1 and got["info"][8] == -1
+    ok = np.ones(400, bool)
+    ok[[7, 8]] = False
+    assert np.array_equal(got["info"][ok], ref["info"][ok])
+
+
+def test_empty_and_arguments(L, ctx):
+    assert L.lupp_batched_solve_ragged(ctx, 0, None, None, None, None, None, None, None) == 0
+    dev = torch.device("cuda:0")
+    z = torch.zeros(4, dtype=torch.int64, device=dev)
+    assert L.lupp_batched_solve_ragged(ctx, 1, None, z, z, z, z, z, z) == -3
+    assert L.lupp_batched_solve_ragged(ctx, 1, z, z, z, z, z, z, z, flags=8) == -10
+
+
+@pytest.mark.slow
+def test_full_size_mixed_batch_sampled(L, ctx):
+    """2,000,000 systems, n ~ U{2..32}, kappa_2 <= 1e4, the persistent launch
+    as the benchmark times it; 3000 sampled systems compared bitwise."""
+    mx = mixed_systems(2_000_000, seed=3)
+    got = run(L, ctx, mx)
+    assert np.all(got["info"] == 0)
+    rng = np.random.Generator(np.random.PCG64(3))
+    idx = np.sort(rng.choice(mx["n"].size, 3000, replace=False))
+    for s in idx:
+        n, oa, ob = int(mx["n"][s]), int(mx["offA"][s]), int(mx["offB"][s])
+        r = oracle.gesv_batch(mx["A"][oa:oa + n * n].reshape(1, n, n), mx["b"][ob:ob + n].reshape(1, n),
+                              threads=1)
+        assert np.array_equal(got["ipiv"][ob:ob + n], r["ipiv"][0])
+        assert np.array_equal(got["x"][ob:ob + n], r["x"][0])
+        assert np.array_equal(got["LU"][oa:oa + n * n], r["LU"][0].reshape(-1))
