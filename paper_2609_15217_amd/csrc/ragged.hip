@@ -98,8 +98,11 @@ __device__ __forceinline__ void ragged_dispatch(const RaggedArgs &a, int n, int 
 
 /* Persistent launch: workgroups take work items (largest sizes first) from an
  * atomic counter until every item is taken; every wave leaves the loop on the
- * same broadcast item index. */
-__global__ void __launch_bounds__(kRaggedThreads) k_ragged_persistent(RaggedArgs a)
+ * same broadcast item index. The kernel holds the code of every size; it is
+ * held to 4 waves per SIMD (the register budget of the largest single size)
+ * at the cost of a few spills outside the solver loops. */
+__global__ void __launch_bounds__(kRaggedThreads) __attribute__((amdgpu_waves_per_eu(4)))
+    k_ragged_persistent(RaggedArgs a)
 {
     __shared__ int sh_item;
     const RaggedPlan *plan = a.plan;
