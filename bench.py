@@ -81,6 +81,109 @@ def load_traffic(kernel_key: str):
     return rec.get("bytes_per_launch")
 
 
+def run_serving(L, ctx, torch, dev, seconds: float, rate: float = 2000.0):
+    """Poisson stream of requests (half solve batches, n ~ U{2..32}, 1k-1M
+    systems; half Newton updates of device-resident point sets, 1k-500k
+    points, 7x7 or 13x13 law) submitted to the serving loop at their arrival
+    times. Inputs are slices of device-resident random pools (an upstream GPU
+    producer); latency runs from the scheduled arrival to completion."""
+    import threading
+
+    from workloads import serving_requests
+    reqs = serving_requests(int(rate * seconds) + 1, seed=5, rate=rate)
+    reqs = [q for q in reqs if q["t"] <= seconds]
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    max_sys, max_pts = 1_000_000, 500_000
+    A_pool = torch.randn(max_sys * 32 * 32, generator=g, dtype=torch.float64, device=dev)
+    b_pool = torch.randn(max_sys * 32, generator=g, dtype=torch.float64, device=dev)
+    d_pool = (torch.rand(6 * max_pts, generator=g, dtype=torch.float64, device=dev) - 0.5) * 4e-3
+    slots = 48
+    x_ring = torch.empty((slots, max_sys * 32), dtype=torch.float64, device=dev)
+    i_ring = torch.empty((slots, max_sys), dtype=torch.int32, device=dev)
+    sig_ring = torch.empty((slots, 6 * max_pts), dtype=torch.float64, device=dev)
+    it_ring = torch.empty((slots, 2 * max_pts), dtype=torch.int32, device=dev)
+    srv = L.Server(ctx, 48 << 30, 16, 8)
+    rng = np.random.Generator(np.random.PCG64(55))
+    sets = {7: [], 13: []}
+    for kind in (7, 13):
+        for _ in range(16):
+            cnt = int(round(np.exp(rng.uniform(np.log(1_000), np.log(max_pts)))))
+            sets[kind].append((L.lupp_server_add_points(srv, kind, cnt), cnt))
+    laws = {7: L.make_law(7), 13: L.make_law(13)}
+    done = []
+    lock = threading.Semaphore(slots)
+    tickets = []
+    cv = threading.Condition()
+
+    def collector():
+        k = 0
+        while True:
+            with cv:
+                while k >= len(tickets):
+                    cv.wait()
+                item = tickets[k]
+            if item is None:
+                return
+            t, arrival, submit_at, q = item
+            rc, lat = L.lupp_server_wait(srv, t)
+            done.append((rc, lat + 1e3 * (submit_at - arrival), q))
+            lock.release()
+            k += 1
+
+    th = threading.Thread(target=collector)
+    th.start()
+    ms_sys = ms_pts = 0
+    t0 = time.perf_counter()
+    for k, q in enumerate(reqs):
+        now = time.perf_counter() - t0
+        if q["t"] > now:
+            time.sleep(q["t"] - now)
+        lock.acquire()
+        slot = k % slots
+        if q["kind"] == "solve":
+            n, bsz = q["n"], min(q["size"], max_sys)
+            r = L.solve_request(n, bsz, A_pool.data_ptr(), b_pool.data_ptr(), x_ring[slot].data_ptr(),
+                                None, i_ring[slot].data_ptr())
+            ms_sys += bsz
+        else:
+            sid, cnt = sets[q["law"]][int(rng.integers(0, 16))]
+            base = sig_ring[slot].data_ptr()
+            r = L.update_request(sid, cnt, laws[q["law"]], d_pool.data_ptr(), base,
+                                 it_ring[slot].data_ptr(), it_ring[slot].data_ptr() + 4 * max_pts)
+            ms_pts += cnt
+        submit_at = time.perf_counter() - t0
+        t = L.lupp_server_submit(srv, r)
+        if t <= 0:
+            raise RuntimeError(f"serving submit: {L.lupp_error_string(t)}")
+        with cv:
+            tickets.append((t, q["t"], submit_at, q))
+            cv.notify()
+    with cv:
+        tickets.append(None)
+        cv.notify()
+    th.join()
+    wall = time.perf_counter() - t0
+    stats = L.lupp_server_get_stats(srv)
+    srv.close()
+    lat = np.array([d[1] for d in done if d[0] == 0])
+    failed = sum(1 for d in done if d[0] != 0)
+    out = {"workload": "Poisson 2000 req/s for %.0f s: 50%% solve (n~U{2..32}, 1k-1M systems, "
+                       "log-uniform), 50%% Newton update of device-resident point sets (1k-500k "
+                       "points, 7x7/13x13 at 50/50)" % seconds,
+           "requests": len(reqs), "failed": failed, "wall_s": round(wall, 3),
+           "p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "systems_per_s": round(ms_sys / wall), "updates_per_s": round(ms_pts / wall),
+           "achieved_req_per_s": round(len(reqs) / wall, 1),
+           "peak_inflight": stats["peak_inflight"], "peak_bytes": stats["peak_bytes"],
+           "budget_bytes": stats["budget_bytes"]}
+    log(f"serving: p50 {out['p50_ms']} ms p99 {out['p99_ms']} ms, {out['achieved_req_per_s']} req/s")
+    del A_pool, b_pool, d_pool, x_ring, i_ring, sig_ring, it_ring
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +192,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--only", default=None, help="n:layout, e.g. 32:soa")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true")
@@ -281,6 +385,11 @@ def main():
         del tn, toA, toB, pA, pb, wA, wb, rip, rin, mx
         torch.cuda.empty_cache()
 
+    # ------------------------------------------------------------- serving
+    serving = {}
+    if args.serve_seconds > 0:
+        serving = run_serving(L, ctx, torch, dev, args.serve_seconds)
+
     # ------------------------------------------------------------- latency
     lat = {}
     A1, b1, _ = systems(8, 4096, seed=1)
@@ -381,6 +490,7 @@ def main():
         "roofline": roofline,
         "newton": newton,
         "ragged": ragged,
+        "serving": serving,
         "latency": lat,
         "per_kernel": per_kernel,
         "cpu_baseline": cpu,

@@ -70,6 +70,9 @@ int lupp_create(lupp_ctx **ctx, int device);
  * first). NULL is accepted. */
 void lupp_destroy(lupp_ctx *ctx);
 
+/* The HIP device a context is bound to. */
+int lupp_get_device(const lupp_ctx *ctx, int *device);
+
 /* Batched dgesv (Section 2.2; Section 3.1): for each of `batch` independent
  * n x n systems, factor PA = LU with partial pivoting and, where the
  * factorisation has no zero pivot, overwrite b with x = A^-1 b.
@@ -194,6 +197,94 @@ typedef struct {
 
 int constitutive_update(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law, double tol,
                         int maxit, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving loop: continuous batching of solve and constitutive-update requests
+ * under an HBM budget.
+ *
+ * The server owns a device arena of hbm_budget_bytes. A submitted request
+ * waits until its footprint fits in the free arena and one of max_inflight
+ * slots is free (admission in submission order; a request whose point set
+ * is busy lets later requests pass). Its inputs are then copied into the
+ * arena, its kernels run on one of `streams` HIP streams, so admitted
+ * requests overlap on the GPU, its outputs are copied out, and its arena
+ * range is released, which admits the requests queued behind it.
+ *
+ * Request pointers may be host or device pointers (the copy direction is
+ * detected). They must stay valid until the ticket completes. Host buffers
+ * should be pinned (hipHostMalloc) for the copies to overlap; pageable ones
+ * work but copy synchronously.
+ *
+ * Integration-point state is device-resident: a point set is registered
+ * once and every update request on it advances its state (committed per
+ * point on convergence). Requests on the same set run in submission order.
+ * Results of a request are bitwise identical whether it runs alone or among
+ * others: each system or point is computed independently and identically.
+ */
+typedef struct lupp_server lupp_server;
+
+typedef struct {
+    int64_t hbm_budget_bytes; /* device arena; 0 = a quarter of the free memory */
+    int max_inflight;         /* requests admitted at once, >= 1 */
+    int streams;              /* HIP streams, 1..64 */
+} lupp_server_config;
+
+#define LUPP_REQ_SOLVE 1
+#define LUPP_REQ_UPDATE 2
+
+typedef struct {
+    int kind; /* LUPP_REQ_SOLVE or LUPP_REQ_UPDATE */
+    /* LUPP_REQ_SOLVE: `batch` packed column-major systems of size n (1..32) */
+    int n;
+    int64_t batch;
+    const double *A; /* [batch][n*n] in */
+    const double *b; /* [batch][n] in: right-hand sides */
+    double *x;       /* [batch][n] out: solutions where info == 0, the right-hand
+                        side where info > 0 (may alias b) */
+    int32_t *ipiv;   /* [batch][n] out, or NULL */
+    int32_t *info;   /* [batch] out, or NULL */
+    double *lu;      /* [batch][n*n] out: the factors, or NULL to skip them */
+    /* LUPP_REQ_UPDATE: one Newton update of every point of a point set */
+    int64_t set_id;
+    int64_t count;   /* must equal the set's point count */
+    const lupp_law *law; /* law->kind must equal the set's kind */
+    double tol;
+    int maxit;
+    const double *deps; /* [6][count] in */
+    double *sig;        /* [6][count] out, or NULL */
+    int32_t *iters;     /* [count] out, or NULL */
+    int32_t *status;    /* [count] out, or NULL */
+} lupp_request;
+
+typedef struct {
+    int64_t submitted, completed, rejected, failed, queued;
+    int inflight, peak_inflight;
+    int64_t peak_bytes, budget_bytes;
+    double p50_ms, p99_ms, mean_ms, max_ms; /* submit -> completion, completed requests */
+    double elapsed_s;                        /* first submit -> last completion */
+} lupp_server_stats;
+
+/* Create a server on ctx's device (it uses a context of its own internally).
+ * Starts one scheduler thread. */
+int lupp_server_create(lupp_ctx *ctx, const lupp_server_config *cfg, lupp_server **server);
+/* Finish every queued and admitted request, then release everything. */
+void lupp_server_destroy(lupp_server *server);
+/* Register count points of law kind (7 or 13) with initial state [kind][count]
+ * (host or device; NULL = virgin). Synchronous. */
+int lupp_server_add_points(lupp_server *server, int kind, int64_t count, const double *state,
+                           int64_t *set_id);
+/* Copy a point set's state out ([kind][count]) after its queued requests. */
+int lupp_server_read_points(lupp_server *server, int64_t set_id, double *state);
+/* Queue a request: returns a ticket > 0, -2 for an invalid request, or
+ * LUPP_E_NOMEM if its footprint exceeds the whole budget. */
+int64_t lupp_server_submit(lupp_server *server, const lupp_request *req);
+/* 1 if the ticket has completed, 0 if not, negative if unknown. */
+int lupp_server_poll(lupp_server *server, int64_t ticket);
+/* Block until the ticket completes; returns its status (0 or a lupp error)
+ * and its latency; the ticket is then retired. */
+int lupp_server_wait(lupp_server *server, int64_t ticket, double *latency_ms);
+int lupp_server_get_stats(lupp_server *server, lupp_server_stats *stats);
+int lupp_server_reset_stats(lupp_server *server);
 
 /* Human-readable text for a return code (static storage). */
 const char *lupp_error_string(int code);

@@ -101,6 +101,14 @@ void lupp_destroy(lupp_ctx *ctx)
     delete ctx;
 }
 
+int lupp_get_device(const lupp_ctx *ctx, int *device)
+{
+    if (ctx == nullptr) return -1;
+    if (device == nullptr) return -2;
+    *device = ctx->device;
+    return 0;
+}
+
 int lupp_force_variant(lupp_ctx *ctx, int variant, int lanes, int wpb)
 {
     if (ctx == nullptr) return -1;

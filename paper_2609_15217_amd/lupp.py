@@ -89,10 +89,46 @@ _lupp_check_solve_args = _sig("lupp_check_solve_args", ctypes.c_int,
                               [ctypes.c_int, _i64, ctypes.c_int, _P, _i64, _i64, _P, _i64, _P, _P,
                                ctypes.c_uint])
 
+class lupp_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", _i64), ("max_inflight", ctypes.c_int), ("streams", ctypes.c_int)]
+
+
+class lupp_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("n", ctypes.c_int), ("batch", _i64), ("A", _P), ("b", _P),
+                ("x", _P), ("ipiv", _P), ("info", _P), ("lu", _P), ("set_id", _i64),
+                ("count", _i64), ("law", ctypes.POINTER(lupp_law)), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int), ("deps", _P), ("sig", _P), ("iters", _P), ("status", _P)]
+
+
+class lupp_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", _i64), ("completed", _i64), ("rejected", _i64), ("failed", _i64),
+                ("queued", _i64), ("inflight", ctypes.c_int), ("peak_inflight", ctypes.c_int),
+                ("peak_bytes", _i64), ("budget_bytes", _i64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("elapsed_s", ctypes.c_double)]
+
+
+_lupp_get_device = _sig("lupp_get_device", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)])
+_lupp_server_create = _sig("lupp_server_create", ctypes.c_int,
+                           [_P, ctypes.POINTER(lupp_server_config), ctypes.POINTER(_P)])
+_lupp_server_destroy = _sig("lupp_server_destroy", None, [_P])
+_lupp_server_add_points = _sig("lupp_server_add_points", ctypes.c_int,
+                               [_P, ctypes.c_int, _i64, _P, ctypes.POINTER(_i64)])
+_lupp_server_read_points = _sig("lupp_server_read_points", ctypes.c_int, [_P, _i64, _P])
+_lupp_server_submit = _sig("lupp_server_submit", _i64, [_P, ctypes.POINTER(lupp_request)])
+_lupp_server_poll = _sig("lupp_server_poll", ctypes.c_int, [_P, _i64])
+_lupp_server_wait = _sig("lupp_server_wait", ctypes.c_int, [_P, _i64, ctypes.POINTER(ctypes.c_double)])
+_lupp_server_get_stats = _sig("lupp_server_get_stats", ctypes.c_int,
+                              [_P, ctypes.POINTER(lupp_server_stats)])
+_lupp_server_reset_stats = _sig("lupp_server_reset_stats", ctypes.c_int, [_P])
+
 EXPORTED = ["lupp_create", "lupp_destroy", "lupp_batched_solve", "lupp_batched_solve_ragged",
             "lupp_force_variant", "lupp_set_dispatch", "lupp_get_dispatch", "lupp_variant_info",
             "constitutive_update", "lupp_error_string", "lupp_check_solve_args",
-            "lupp_autotune"]
+            "lupp_autotune", "lupp_get_device", "lupp_server_create", "lupp_server_destroy",
+            "lupp_server_add_points", "lupp_server_read_points", "lupp_server_submit",
+            "lupp_server_poll", "lupp_server_wait", "lupp_server_get_stats",
+            "lupp_server_reset_stats"]
 
 
 class LuppError(RuntimeError):
@@ -108,11 +144,14 @@ def _check(rc: int, what: str) -> int:
 
 
 def _ptr(x) -> _P:
+    """Device or host address of a torch tensor, numpy array or raw int."""
     if x is None:
         return _P(0)
     if isinstance(x, int):
         return _P(x)
-    return _P(x.data_ptr())
+    if hasattr(x, "data_ptr"):
+        return _P(x.data_ptr())
+    return _P(x.ctypes.data)
 
 
 def _stream(stream) -> _P:
@@ -261,3 +300,100 @@ def points(deps: torch.Tensor, state: torch.Tensor, sig: torch.Tensor, iters: to
         assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.shape[1] == ld
     return lupp_points(count, ld, deps.data_ptr(), state.data_ptr(), sig.data_ptr(),
                        iters.data_ptr(), status.data_ptr())
+
+
+# --------------------------------------------------------------------------
+# Serving loop
+# --------------------------------------------------------------------------
+LUPP_REQ_SOLVE, LUPP_REQ_UPDATE = 1, 2
+
+
+def lupp_get_device(ctx: Context) -> int:
+    d = ctypes.c_int()
+    _check(_lupp_get_device(ctx.handle, ctypes.byref(d)), "lupp_get_device")
+    return d.value
+
+
+class Server:
+    """Owns a lupp_server (device arena, streams, scheduler thread)."""
+
+    def __init__(self, ctx: Context, budget_bytes: int = 0, max_inflight: int = 8, streams: int = 4):
+        cfg = lupp_server_config(budget_bytes, max_inflight, streams)
+        h = _P()
+        _check(_lupp_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "lupp_server_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _lupp_server_destroy(self.handle)
+            self.handle = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lupp_server_create(ctx: Context, budget_bytes: int = 0, max_inflight: int = 8,
+                       streams: int = 4) -> Server:
+    return Server(ctx, budget_bytes, max_inflight, streams)
+
+
+def lupp_server_destroy(server: Server):
+    server.close()
+
+
+def lupp_server_add_points(server: Server, kind: int, count: int, state=None) -> int:
+    sid = _i64()
+    _check(_lupp_server_add_points(server.handle, kind, count, _ptr(state), ctypes.byref(sid)),
+           "lupp_server_add_points")
+    return sid.value
+
+
+def lupp_server_read_points(server: Server, set_id: int, out) -> int:
+    return _lupp_server_read_points(server.handle, set_id, _ptr(out))
+
+
+def solve_request(n: int, batch: int, A, b, x, ipiv=None, info=None, lu=None) -> lupp_request:
+    r = lupp_request()
+    r.kind, r.n, r.batch = LUPP_REQ_SOLVE, n, batch
+    r.A, r.b, r.x = _ptr(A), _ptr(b), _ptr(x)
+    r.ipiv, r.info, r.lu = _ptr(ipiv), _ptr(info), _ptr(lu)
+    return r
+
+
+def update_request(set_id: int, count: int, law: lupp_law, deps, sig=None, iters=None, status=None,
+                   tol: float = 1e-12, maxit: int = 20) -> lupp_request:
+    r = lupp_request()
+    r.kind, r.set_id, r.count = LUPP_REQ_UPDATE, set_id, count
+    r.law = ctypes.pointer(law)
+    r.tol, r.maxit = tol, maxit
+    r.deps, r.sig, r.iters, r.status = _ptr(deps), _ptr(sig), _ptr(iters), _ptr(status)
+    return r
+
+
+
+
+def lupp_server_submit(server: Server, req: lupp_request) -> int:
+    return _lupp_server_submit(server.handle, ctypes.byref(req))
+
+
+def lupp_server_poll(server: Server, ticket: int) -> int:
+    return _lupp_server_poll(server.handle, ticket)
+
+
+def lupp_server_wait(server: Server, ticket: int):
+    lat = ctypes.c_double()
+    rc = _lupp_server_wait(server.handle, ticket, ctypes.byref(lat))
+    return rc, lat.value
+
+
+def lupp_server_get_stats(server: Server) -> dict:
+    st = lupp_server_stats()
+    _check(_lupp_server_get_stats(server.handle, ctypes.byref(st)), "lupp_server_get_stats")
+    return {f: getattr(st, f) for f, _ in lupp_server_stats._fields_}
+
+
+def lupp_server_reset_stats(server: Server) -> int:
+    return _lupp_server_reset_stats(server.handle)
