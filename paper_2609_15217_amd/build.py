@@ -46,7 +46,7 @@ def lanes_widths(n: int) -> list[int]:
     if n <= 8:
         return [4, 8]
     if n <= 16:
-        return [4, 8, 16]
+        return [8, 16]  # T = 4 needs K >= 3 rows per lane here and spills
     return [16, 32]
 
 
@@ -69,7 +69,7 @@ def generate(gen: str) -> list[str]:
         srcs.append(p)
     for n, t in LANES:
         p = os.path.join(gen, f"lanes_{n}_{t}.hip")
-        _write_if_changed(p, f'#include "kernels_lanes.h"\nLUPP_LANES_INSTANCE({n}, {t})\n')
+        _write_if_changed(p, f'#include "kernels_lanes.h"\n#include "kernels_lanes_soa.h"\nLUPP_LANES_INSTANCE({n}, {t})\n')
         srcs.append(p)
     for g in range(4):
         ns = [n for n in range(1, 33) if (n - 1) % 4 == g]
@@ -87,7 +87,7 @@ def generate(gen: str) -> list[str]:
     for n in THREAD_NS:
         lines.append(f"LaunchFn thread_fn_{n}(); const void *thread_sym_{n}();")
     for n, t in LANES:
-        lines.append(f"LaunchFn lanes_fn_{n}_{t}(); const void *lanes_sym_{n}_{t}();")
+        lines.append(f"LaunchFn lanes_fn_{n}_{t}(); const void *lanes_sym_{n}_{t}(int layout);")
     lines.append("LaunchFn thread_launcher(int n) {\n  switch (n) {")
     lines += [f"  case {n}: return thread_fn_{n}();" for n in THREAD_NS]
     lines.append("  default: return nullptr;\n  }\n}")
@@ -97,8 +97,8 @@ def generate(gen: str) -> list[str]:
     lines.append("LaunchFn lanes_launcher(int n, int t) {")
     lines += [f"  if (n == {n} && t == {t}) return lanes_fn_{n}_{t}();" for n, t in LANES]
     lines.append("  return nullptr;\n}")
-    lines.append("const void *lanes_kernel_symbol(int n, int t) {")
-    lines += [f"  if (n == {n} && t == {t}) return lanes_sym_{n}_{t}();" for n, t in LANES]
+    lines.append("const void *lanes_kernel_symbol(int n, int t, int layout) {")
+    lines += [f"  if (n == {n} && t == {t}) return lanes_sym_{n}_{t}(layout);" for n, t in LANES]
     lines.append("  return nullptr;\n}")
     lines.append("int lanes_widths(int n, int *out, int cap) {\n  int c = 0;")
     for n in range(2, 33):

@@ -310,12 +310,11 @@ int lupp_autotune(lupp_ctx *ctx, int n, int64_t batch, int layout, const double 
 int lupp_variant_info(int n, int layout, int variant, int lanes, int keep_a,
                       lupp_kernel_info *out)
 {
-    (void)layout;
     (void)keep_a;
     if (out == nullptr) return -6;
     const void *sym = nullptr;
     if (variant == LUPP_VARIANT_THREAD) sym = thread_kernel_symbol(n);
-    else if (variant == LUPP_VARIANT_LANES) sym = lanes_kernel_symbol(n, lanes);
+    else if (variant == LUPP_VARIANT_LANES) sym = lanes_kernel_symbol(n, lanes, layout);
     else if (variant == 100 + LUPP_LAW_NORTON7 || variant == 100 + LUPP_LAW_NORTON_AF13)
         sym = constitutive_kernel_symbol(variant - 100);
     if (sym == nullptr) return LUPP_E_UNSUPPORTED;

@@ -30,7 +30,7 @@ typedef hipError_t (*LaunchFn)(const SolveArgs &, int layout, bool factors, int 
 LaunchFn thread_launcher(int n);
 LaunchFn lanes_launcher(int n, int lanes);
 const void *thread_kernel_symbol(int n);
-const void *lanes_kernel_symbol(int n, int lanes);
+const void *lanes_kernel_symbol(int n, int lanes, int layout);
 /* Segment widths compiled for size n (ascending), returns the count. */
 int lanes_widths(int n, int *out, int cap);
 /* Batches below this size use the small-batch dispatch entries. */

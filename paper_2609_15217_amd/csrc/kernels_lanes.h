@@ -7,8 +7,10 @@
  * (block*wpb + w)*(64/T) + g for segments g = 0..64/T-1; lane t of segment g
  * owns rows t, t+T, ... .
  * AoS: a segment reads T consecutive doubles of a column per load.
- * SoA: a wave reads 64/T consecutive systems of T rows per load.
- * Both layouts are served by the same kernel: only the uniform base pointers
+ * SoA: a wave reads 64/T consecutive systems of T rows per load (partial
+ * cache lines; the library launches the LDS-staged kernel of
+ * kernels_lanes_soa.h for this layout instead).
+ * Both layouts are handled by the same code: only the uniform base pointers
  * and the per-lane byte offsets differ. Lanes past the end of the batch and
  * phantom rows use an out-of-range buffer offset, so they load zeros and
  * store nothing.
@@ -118,8 +120,14 @@ __global__ void __launch_bounds__(256) k_lanes(SolveArgs a, int layout, int fact
 }
 
 template <int N, int T>
+hipError_t launch_lanes_soa(const SolveArgs &a, bool factors, hipStream_t st);
+
+/* AoS: this kernel with `wpb` waves per workgroup; SoA: the LDS-staged kernel
+ * (kernels_lanes_soa.h), whose workgroup shape is fixed (wpb is ignored). */
+template <int N, int T>
 hipError_t launch_lanes(const SolveArgs &a, int layout, bool factors, int wpb, hipStream_t st)
 {
+    if (layout == LUPP_SOA) return launch_lanes_soa<N, T>(a, factors, st);
     const int w = wpb > 0 ? wpb : 4;
     const int64_t per_block = (int64_t)w * (64 / T);
     const int64_t blocks = (a.batch + per_block - 1) / per_block;
@@ -135,7 +143,11 @@ hipError_t launch_lanes(const SolveArgs &a, int layout, bool factors, int wpb, h
 #define LUPP_LANES_INSTANCE(N, T)                                                   \
     namespace lupp {                                                               \
     LaunchFn lanes_fn_##N##_##T() { return launch_lanes<N, T>; }                   \
-    const void *lanes_sym_##N##_##T() { return reinterpret_cast<const void *>(&k_lanes<N, T>); } \
+    const void *lanes_sym_##N##_##T(int layout)                                    \
+    {                                                                              \
+        return layout == LUPP_SOA ? reinterpret_cast<const void *>(&k_lanes_soa<N, T>) \
+                                  : reinterpret_cast<const void *>(&k_lanes<N, T>); \
+    }                                                                              \
     }
 
 #endif

@@ -1,0 +1,242 @@
+/* Lanes-per-system batched solve for the interleaved (SoA) layout, with the
+ * global traffic staged through LDS (Section 3: coalesced accesses to the
+ * batch; Section 3.2: several rows per thread, several systems per wave).
+ *
+ * The solve itself is the one of k_lanes (T lanes per system, K = ceil(n/T)
+ * rows per lane, logical pivoting). What differs is how the matrices move
+ * between HBM and registers. In the interleaved layout element (i, j) of
+ * consecutive systems is contiguous, but a wave holds only 64/T systems, so a
+ * direct load of one element per lane touches T rows x (64/T) systems: T
+ * partial cache lines per instruction, and the rest of every line is read by
+ * other waves. Here a workgroup owns S = 16 consecutive systems (one 128-byte
+ * line per matrix element) and moves column chunks of its S matrices through
+ * LDS: every global load or store instruction covers whole lines, and the
+ * transposition into the lanes' row ownership happens in LDS.
+ *
+ * LDS tile of a column chunk: element (column c, row i, system y) at
+ *     (c * NP + i) * S + (y ^ sw(i)),
+ * NP = rows padded to whole segments. The XOR swizzle sw(i) permutes the
+ * systems of each row so that both access patterns are free of bank
+ * conflicts within each half-wave (32 lanes x 8 bytes = all 64 banks):
+ *   - cooperative side: 32 consecutive (row, system) pairs, systems fastest;
+ *   - lane side: 32/T systems x T consecutive rows of a segment slot.
+ * sw(i) = ((i >> max(0, 5 - log2 S)) << log2(32/T)) & (S - 1).
+ *
+ * Rows past n and systems past the batch end use an out-of-range buffer
+ * offset: they load zeros (as in k_lanes) and store nothing.
+ */
+#ifndef LUPP_KERNELS_LANES_SOA_H
+#define LUPP_KERNELS_LANES_SOA_H
+
+#include "internal.h"
+#include "lupp_device.h"
+
+namespace lupp {
+
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+template <int N, int T>
+struct soa_shape {
+    static constexpr int SPW = 64 / T;                   /* systems per wave */
+    static constexpr int S = SPW > 16 ? SPW : 16;        /* systems per workgroup */
+    static constexpr int WPB = S / SPW;                  /* waves per workgroup */
+    static constexpr int NT = 64 * WPB;                  /* threads = S * T */
+    static constexpr int K = (N + T - 1) / T;
+    static constexpr int NP = K * T;                     /* rows padded to segments */
+    static constexpr int LOG_S = ilog2c(S);
+    static constexpr int LOG_SPH = ilog2c(T >= 32 ? 1 : 32 / T); /* systems per half-wave */
+    static constexpr int SH = LOG_S >= 5 ? 0 : 5 - LOG_S;
+    /* columns per LDS chunk: about 4 KB of tile per wave */
+    static constexpr int CJ0 = (4096 * WPB) / (NP * S * 8);
+    static constexpr int CJ = CJ0 < 1 ? 1 : (CJ0 > N ? N : CJ0);
+    static constexpr int NCH = (N + CJ - 1) / CJ;        /* chunks */
+    /* 512-thread workgroups (T = 32) need two per CU: at most 128 VGPRs */
+    static constexpr int MIN_WAVES_EU = WPB >= 8 ? 4 : 1;
+    static_assert(NT == S * T, "shape");
+};
+
+template <int N, int T>
+__device__ __forceinline__ int soa_sw(int i)
+{
+    using Sh = soa_shape<N, T>;
+    return ((i >> Sh::SH) << Sh::LOG_SPH) & (Sh::S - 1);
+}
+
+template <int N, int T>
+__global__ void __launch_bounds__((soa_shape<N, T>::NT))
+    __attribute__((amdgpu_waves_per_eu(soa_shape<N, T>::MIN_WAVES_EU))) k_lanes_soa(SolveArgs a, int factors)
+{
+    using Sh = soa_shape<N, T>;
+    constexpr int S = Sh::S, K = Sh::K, NP = Sh::NP, CJ = Sh::CJ, NCH = Sh::NCH;
+    constexpr int QB = NP / T; /* cooperative accesses per column and thread */
+    __shared__ double tile[CJ * NP * S];
+    __shared__ double xb[NP * S];
+    __shared__ int ipl[NP * S];
+    __shared__ int infl[S];
+
+    const int tid = (int)threadIdx.x;
+    const int lane = (int)__lane_id();
+    const int g = lane / T, t = lane % T;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t sys0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * S;
+    const int64_t rem = a.batch - sys0;
+    const int nvalid = (int)(rem < S ? rem : S);
+
+    /* cooperative side: system yw, rows ci0 + multiples of T */
+    const int yw = tid & (S - 1);
+    const int ci0 = tid >> Sh::LOG_S;
+    /* lane side: system yl, rows t + s*T */
+    const int yl = wave * Sh::SPW + g;
+
+    double *baseA = a.A + sys0;
+    double *baseB = a.b + sys0;
+    const int64_t colA = a.lda * a.sA;
+    const uint32_t bytesA = (uint32_t)(((int64_t)(N - 1) * a.sA + nvalid) * 8);
+    const uint32_t bytesB = (uint32_t)(((int64_t)(N - 1) * a.sB + nvalid) * 8);
+    const uint32_t vA = yw < nvalid ? (uint32_t)(((int64_t)ci0 * a.sA + yw) * 8) : kOutOfRange;
+    const uint32_t vB = yw < nvalid ? (uint32_t)(((int64_t)ci0 * a.sB + yw) * 8) : kOutOfRange;
+    /* per-lane offset of the cooperative row ci0 + ib (out of range for rows past n) */
+    auto rowv = [&](uint32_t v, int ib) -> uint32_t {
+        return (ib + T <= N || ci0 < N - ib) ? v : kOutOfRange;
+    };
+    /* LDS index of the cooperative element (chunk column c, row block ib) */
+    auto cidx = [&](int c, int ib) { const int i = ci0 + ib; return (c * NP + i) * S + (yw ^ soa_sw<N, T>(i)); };
+    /* LDS index of a lane-side element (chunk column c, row i) */
+    auto lidx = [&](int c, int i) { return (c * NP + i) * S + (yl ^ soa_sw<N, T>(i)); };
+
+    /* ---------------------------------------------------------- load */
+    double m[K][N];
+    double x[K];
+    int pos[K];
+    static_for<0, K>(LUPP_SF(sc) {
+        constexpr int s = decltype(sc)::value;
+        pos[s] = t + s * T < N ? t + s * T : -1;
+    });
+    /* every global load is issued up front (as many in flight as the
+     * direct-load kernel); the transposition then goes chunk by chunk, and
+     * the staging registers of a chunk die as its matrix registers fill */
+    double v[N * QB];
+    double vb[QB];
+    static_for<0, N * QB>(LUPP_SF(qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int j = q / QB, ib = (q % QB) * T;
+        const auto rc = make_rsrc(baseA + (int64_t)j * colA, bytesA);
+        v[q] = buf_load_f64(rc, rowv(vA, ib), (uint32_t)((int64_t)ib * a.sA * 8));
+    });
+    {
+        const auto rb = make_rsrc(baseB, bytesB);
+        static_for<0, QB>(LUPP_SF(qc) {
+            constexpr int ib = decltype(qc)::value * T;
+            vb[decltype(qc)::value] = buf_load_f64(rb, rowv(vB, ib), (uint32_t)((int64_t)ib * a.sB * 8));
+        });
+    }
+    static_for<0, NCH>(LUPP_SF(chc) {
+        constexpr int ch = decltype(chc)::value;
+        constexpr int j0 = ch * CJ;
+        constexpr int cj = (j0 + CJ <= N) ? CJ : N - j0;
+        static_for<0, cj * QB>(LUPP_SF(qc) {
+            constexpr int q = decltype(qc)::value;
+            tile[cidx(q / QB, (q % QB) * T)] = v[j0 * QB + q];
+        });
+        if constexpr (ch == NCH - 1) {
+            static_for<0, QB>(LUPP_SF(qc) {
+                constexpr int q = decltype(qc)::value;
+                xb[cidx(0, q * T)] = vb[q];
+            });
+        }
+        __syncthreads();
+        static_for<0, cj>(LUPP_SF(cc) {
+            constexpr int c = decltype(cc)::value;
+            static_for<0, K>(LUPP_SF(sc) {
+                constexpr int s = decltype(sc)::value;
+                m[s][j0 + c] = tile[lidx(c, t + s * T)];
+            });
+        });
+        if constexpr (ch == NCH - 1) {
+            static_for<0, K>(LUPP_SF(sc) {
+                constexpr int s = decltype(sc)::value;
+                x[s] = xb[lidx(0, t + s * T)];
+            });
+        }
+        __syncthreads();
+    });
+
+    /* ---------------------------------------------------------- solve */
+    constexpr int KP = (N + T - 1) / T;
+    int pv[KP];
+    static_for<0, KP>(LUPP_SF(sc) { pv[decltype(sc)::value] = 0; });
+    const int inf = lanes_getrf_solve<N, T>(m, x, pos, g * T, [&](int k, int val) {
+        const int c = k / T;
+        static_for<0, KP>(LUPP_SF(sc) {
+            constexpr int cc = decltype(sc)::value;
+            if (cc == c) pv[cc] = (t == k % T) ? val : pv[cc];
+        });
+    });
+
+    /* ---------------------------------------------------------- store */
+    baseA = opaque_ptr(baseA);
+    baseB = opaque_ptr(baseB);
+    if (factors) {
+        static_for<0, NCH>(LUPP_SF(chc) {
+            constexpr int j0 = decltype(chc)::value * CJ;
+            constexpr int cj = (j0 + CJ <= N) ? CJ : N - j0;
+            /* slot s holds row pos[s] of the LAPACK-ordered factors */
+            static_for<0, K>(LUPP_SF(sc) {
+                constexpr int s = decltype(sc)::value;
+                if (pos[s] >= 0) {
+                    static_for<0, cj>(LUPP_SF(cc) {
+                        constexpr int c = decltype(cc)::value;
+                        tile[lidx(c, pos[s])] = m[s][j0 + c];
+                    });
+                }
+            });
+            __syncthreads();
+            static_for<0, cj * QB>(LUPP_SF(qc) {
+                constexpr int q = decltype(qc)::value;
+                constexpr int c = q / QB, ib = (q % QB) * T;
+                const auto rc = make_rsrc(baseA + (int64_t)(j0 + c) * colA, bytesA);
+                buf_store_f64(rc, rowv(vA, ib), (uint32_t)((int64_t)ib * a.sA * 8), tile[cidx(c, ib)]);
+            });
+            __syncthreads();
+        });
+    }
+    static_for<0, K>(LUPP_SF(sc) {
+        constexpr int s = decltype(sc)::value;
+        if (pos[s] >= 0) xb[lidx(0, pos[s])] = x[s];
+    });
+    static_for<0, KP>(LUPP_SF(sc) {
+        constexpr int c = decltype(sc)::value;
+        const int k = t + c * T;
+        if (k < N) ipl[lidx(0, k)] = pv[c];
+    });
+    if (t == 0) infl[yl] = inf;
+    __syncthreads();
+    {
+        const bool ok = infl[yw] == 0;
+        const auto rb = make_rsrc(baseB, bytesB);
+        const auto rp = make_rsrc(a.ipiv + sys0, (uint32_t)(((int64_t)(N - 1) * a.sA + nvalid) * 4));
+        const uint32_t vP = yw < nvalid ? (uint32_t)(((int64_t)ci0 * a.sA + yw) * 4) : kOutOfRange;
+        static_for<0, QB>(LUPP_SF(qc) {
+            constexpr int ib = decltype(qc)::value * T;
+            buf_store_f64(rb, ok ? rowv(vB, ib) : kOutOfRange, (uint32_t)((int64_t)ib * a.sB * 8),
+                          xb[cidx(0, ib)]);
+            buf_store_i32(rp, rowv(vP, ib), (uint32_t)((int64_t)ib * a.sA * 4), ipl[cidx(0, ib)]);
+        });
+        const auto ri = make_rsrc(a.info + sys0, (uint32_t)nvalid * 4u);
+        if (tid < S) buf_store_i32(ri, (uint32_t)tid * 4u, 0, infl[tid]);
+    }
+}
+
+template <int N, int T>
+hipError_t launch_lanes_soa(const SolveArgs &a, bool factors, hipStream_t st)
+{
+    using Sh = soa_shape<N, T>;
+    const int64_t blocks = (a.batch + Sh::S - 1) / Sh::S;
+    hipLaunchKernelGGL((k_lanes_soa<N, T>), dim3((unsigned)blocks), dim3(Sh::NT), 0, st, a,
+                       (int)factors);
+    return hipGetLastError();
+}
+
+}  // namespace lupp
+
+#endif
