@@ -444,12 +444,71 @@ def main():
             ms = float(np.mean(times))
             its = it.double().sum().item()
             conv = int((stt == 0).sum().item())
+            # the same update plus the consistent tangent of every converged
+            # point (one multi-right-hand-side solve after convergence)
+            tan = torch.empty((36, count), dtype=torch.float64, device=dev)
+            pts_t = L.points(d, st, sig, it, stt, tan)
+            ttimes = []
+            for r in range(args.warmup + args.steps):
+                st.zero_()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                rc = L.constitutive_update(ctx, pts_t, law, 1e-12, 20, stream)
+                e1.record(stream)
+                assert rc == 0
+                torch.cuda.synchronize()
+                if r >= args.warmup:
+                    ttimes.append(e0.elapsed_time(e1))
+            tms = float(np.mean(ttimes))
             newton[f"norton{kind}"] = {"points": count, "ms": round(ms, 3),
                                        "updates_per_s": round(count / (ms * 1e-3)),
                                        "newton_iterations_per_s": round(its / (ms * 1e-3)),
                                        "mean_solves_per_point": round(its / count, 3),
-                                       "converged": conv}
-            log(f"newton {kind}: {ms:.2f} ms")
+                                       "converged": conv,
+                                       "with_tangent_ms": round(tms, 3),
+                                       "with_tangent_updates_per_s": round(count / (tms * 1e-3))}
+            del tan
+            log(f"newton {kind}: {ms:.2f} ms, with tangent {tms:.2f} ms")
+
+    # ------------------------------------------------------------- sweeps
+    sweep = {}
+    if not args.no_newton:
+        # a small point set advanced over many time steps: one launch per step
+        # versus the steps captured once in a HIP graph and replayed
+        count, nsteps = 16384, 100
+        dsw = torch.from_numpy(newton_points(count, seed=4, lo=-2e-4, hi=2e-4).T.copy()).to(dev)
+        st = torch.zeros((7, count), dtype=torch.float64, device=dev)
+        sig = torch.empty((6, count), dtype=torch.float64, device=dev)
+        it = torch.empty(count, dtype=torch.int32, device=dev)
+        stt = torch.empty(count, dtype=torch.int32, device=dev)
+        pts = L.points(dsw, st, sig, it, stt)
+        law = L.make_law(7)
+        graph = L.Sweep(ctx, pts, law, 1e-12, 20, nsteps, 0)
+        res = {}
+        for mode in ("eager", "graph"):
+            times = []
+            for r in range(args.warmup + args.steps):
+                st.zero_()
+                torch.cuda.synchronize()
+                t_s = time.perf_counter()
+                if mode == "eager":
+                    for _ in range(nsteps):
+                        assert L.constitutive_update(ctx, pts, law, 1e-12, 20, stream) == 0
+                else:
+                    assert graph.launch(stream) == 0
+                torch.cuda.synchronize()
+                if r >= args.warmup:
+                    times.append(time.perf_counter() - t_s)
+            res[mode] = float(np.median(times))
+        graph.close()
+        sweep = {"workload": f"{count} points, Norton 7x7, {nsteps} time steps of the same "
+                             "increment (U(-2e-4, 2e-4) per Kelvin component, seed 4)",
+                 "eager_ms": round(res["eager"] * 1e3, 3), "graph_ms": round(res["graph"] * 1e3, 3),
+                 "graph_updates_per_s": round(count * nsteps / res["graph"]),
+                 "speedup_graph_vs_eager": round(res["eager"] / res["graph"], 3)}
+        log(f"sweep: eager {sweep['eager_ms']} ms, graph {sweep['graph_ms']} ms")
+        del dsw, st, sig, it, stt
 
     # ------------------------------------------------------------- CPU oracle
     cpu = None
@@ -489,6 +548,7 @@ def main():
                    "mode": "strict (bitwise-reproducible, no FMA, true division)"},
         "roofline": roofline,
         "newton": newton,
+        "sweep": sweep,
         "ragged": ragged,
         "serving": serving,
         "latency": lat,

@@ -122,7 +122,9 @@ int lupp_batched_solve_ragged(lupp_ctx *ctx, int64_t batch, const int32_t *n,
 /* Restrict later lupp_batched_solve calls on this context to one variant
  * (LUPP_VARIANT_AUTO restores the size-aware dispatch table). lanes is the
  * segment width for LUPP_VARIANT_LANES (2, 4, 8, 16 or 32), wpb the number of
- * wave64s per workgroup (1, 2 or 4; 0 = default). Returns LUPP_E_UNSUPPORTED
+ * wave64s per workgroup (1, 2 or 4; 0 = default). In the SoA layout the lanes
+ * variant has a fixed workgroup of 16 systems (staged through LDS) and
+ * ignores wpb. Returns LUPP_E_UNSUPPORTED
  * if a later call's n cannot be served by the forced variant. */
 int lupp_force_variant(lupp_ctx *ctx, int variant, int lanes, int wpb);
 
@@ -148,6 +150,9 @@ int lupp_autotune(lupp_ctx *ctx, int n, int64_t batch, int layout, const double 
 
 /* Compile-time resources of one kernel variant: VGPRs, AGPRs and SGPRs per
  * lane, private (scratch) bytes per lane, and LDS bytes per workgroup.
+ * variant: LUPP_VARIANT_THREAD or LUPP_VARIANT_LANES (with lanes) for the
+ * batched solve of size n in `layout`; 100 + a law kind for the fused Newton
+ * kernel of that law, keep_a != 0 then selecting its tangent-computing form.
  * Returns LUPP_E_UNSUPPORTED if the variant does not exist. */
 typedef struct {
     int vgprs, agprs, sgprs, scratch_bytes, lds_bytes, max_threads;
@@ -172,6 +177,14 @@ int lupp_variant_info(int n, int layout, int variant, int lanes, int keep_a,
  * D dp alpha.  The start is x = 0. At each iterate: a non-finite residual
  * stops with status 3; ||F||_inf < tol stops with status 0; after maxit linear
  * solves status 1; a zero pivot status 2.
+ *
+ * Consistent tangent (Section 2.5; Section 4.3: one multi-right-hand-side
+ * solve after convergence), when pts->tangent is not NULL: with F(y; deps) =
+ * 0 at the converged unknowns and dF/d(deps) = -[I6; 0], dy/d(deps) =
+ * J^-1 [I6; 0]. The kernel factors the Jacobian of the converged iterate
+ * once (partial pivoting, the same device-callable LU), solves for the six
+ * unit right-hand sides, and returns dsig/d(deps) = D dy_e/d(deps), D the
+ * elastic stiffness. A singular Jacobian there gives NaN entries.
  */
 #define LUPP_MAXIT_LIMIT 10000 /* largest accepted maxit (bounds every kernel's run time) */
 #define LUPP_LAW_NORTON7 7
@@ -193,10 +206,33 @@ typedef struct {
     double *sig;          /* [6][ld]   stress at the returned iterate */
     int32_t *iters;       /* [count]   linear solves performed */
     int32_t *status;      /* [count]   0 converged, 1 maxit, 2 singular J, 3 non-finite */
+    double *tangent;      /* NULL, or [36][ld]: consistent tangent dsig/d(deps) of every
+                             converged point, entry (r, c) at component 6*r + c (Kelvin);
+                             untouched for points with status != 0 */
 } lupp_points;
 
 int constitutive_update(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law, double tol,
                         int maxit, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Time-step sweeps captured in a HIP graph. An implicit constitutive update
+ * runs at every step of the global solution (Section 2.5); a sweep records
+ * `steps` successive constitutive_update launches on the same points (step t
+ * reads the strain increments at pts->deps + t * deps_step and starts from
+ * the state the previous step committed) as kernel nodes of one graph, and
+ * each lupp_sweep_launch replays all of them with one launch on `stream`.
+ *   deps_step : elements between the increments of successive steps, >= 6 * ld,
+ *               or 0 to apply the same increments at every step.
+ * The buffers named by pts are bound at creation and must stay valid until
+ * lupp_sweep_destroy; sig/iters/status/tangent hold the last step's values
+ * after a replay. Replays on one sweep must not overlap (they share the
+ * buffers). Returns 0 or -k for the k-th argument (as constitutive_update,
+ * -6 steps < 1, -7 deps_step, -8 out == NULL). */
+typedef struct lupp_sweep lupp_sweep;
+int lupp_sweep_create(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law, double tol,
+                      int maxit, int steps, int64_t deps_step, lupp_sweep **out);
+int lupp_sweep_launch(lupp_sweep *sweep, void *stream);
+void lupp_sweep_destroy(lupp_sweep *sweep);
 
 /* ---------------------------------------------------------------------------
  * Serving loop: continuous batching of solve and constitutive-update requests
@@ -254,6 +290,9 @@ typedef struct {
     double *sig;        /* [6][count] out, or NULL */
     int32_t *iters;     /* [count] out, or NULL */
     int32_t *status;    /* [count] out, or NULL */
+    double *tangent;    /* [36][count] out, or NULL: consistent tangent of the
+                           converged points (see constitutive_update); entries of
+                           points with status != 0 are unspecified */
 } lupp_request;
 
 typedef struct {

@@ -158,6 +158,61 @@ __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)
     return info;
 }
 
+/* Row permutation of a LAPACK interchange sequence (1-based ipiv): row i of
+ * P A is row perm[i] of A. */
+template <int N>
+__device__ __forceinline__ void thread_ipiv_to_perm(const int (&ipiv)[N], int (&perm)[N])
+{
+    static_for<0, N>(LUPP_SF(ic) { perm[decltype(ic)::value] = decltype(ic)::value; });
+    static_for<0, N>(LUPP_SF(kc) {
+        constexpr int k = decltype(kc)::value;
+        const int p = ipiv[k] - 1;
+        int vp = perm[k];
+        static_for<k + 1, N>(LUPP_SF(ic) {
+            constexpr int i = decltype(ic)::value;
+            vp = (p == i) ? perm[i] : vp;
+        });
+        const int vk = perm[k];
+        static_for<k + 1, N>(LUPP_SF(ic) {
+            constexpr int i = decltype(ic)::value;
+            perm[i] = (p == i) ? vk : perm[i];
+        });
+        perm[k] = vp;
+    });
+}
+
+/* x = A^-1 e_c from the LAPACK-ordered factors lu[j][i] (element (i, j)) of
+ * thread_getrf_solve<N, true> and the row permutation of its ipiv: P e_c,
+ * then forward substitution with the unit lower factor (column-oriented,
+ * ascending) and back substitution with the upper one (divide, then
+ * eliminate the column above, descending) - the operation order of the
+ * one-right-hand-side solve. Used for multi-right-hand-side solves with unit
+ * vectors, such as a consistent tangent operator. */
+template <int N>
+__device__ __forceinline__ void thread_solve_unit(const double (&lu)[N][N], const int (&perm)[N],
+                                                  int c, double (&x)[N])
+{
+    static_for<0, N>(LUPP_SF(ic) {
+        constexpr int i = decltype(ic)::value;
+        x[i] = (perm[i] == c) ? 1.0 : 0.0;
+    });
+    static_for<0, N>(LUPP_SF(jc) {
+        constexpr int j = decltype(jc)::value;
+        static_for<j + 1, N>(LUPP_SF(ic) {
+            constexpr int i = decltype(ic)::value;
+            x[i] = x[i] - lu[j][i] * x[j];
+        });
+    });
+    static_for_down<0, N>(LUPP_SF(jc) {
+        constexpr int j = decltype(jc)::value;
+        x[j] = x[j] / lu[j][j];
+        static_for<0, j>(LUPP_SF(ic) {
+            constexpr int i = decltype(ic)::value;
+            x[i] = x[i] - lu[j][i] * x[j];
+        });
+    });
+}
+
 /* Solve-only convenience entry: the device-callable solve of one system held
  * by the calling thread (a is destroyed). Returns info. */
 template <int N>
@@ -207,10 +262,12 @@ __device__ __forceinline__ int bcast_i32(int v, int src_lane)
 template <int L>
 __device__ __forceinline__ void pair_u32(unsigned v, unsigned &a, unsigned &b)
 {
-    if constexpr (L == 0) { a = v; b = __builtin_amdgcn_update_dpp(0u, v, 0xB1, 0xF, 0xF, false); }
-    else if constexpr (L == 1) { a = v; b = __builtin_amdgcn_update_dpp(0u, v, 0x4E, 0xF, 0xF, false); }
-    else if constexpr (L == 2) { a = v; b = __builtin_amdgcn_update_dpp(0u, v, 0x141, 0xF, 0xF, false); }
-    else if constexpr (L == 3) { a = v; b = __builtin_amdgcn_update_dpp(0u, v, 0x140, 0xF, 0xF, false); }
+    /* every lane has a valid source lane in these patterns, so the plain DPP
+     * move (no "old" operand to initialise) is enough */
+    if constexpr (L == 0) { a = v; b = __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+    else if constexpr (L == 1) { a = v; b = __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false); }
+    else if constexpr (L == 2) { a = v; b = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false); }
+    else if constexpr (L == 3) { a = v; b = __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false); }
     else {
         /* {a, b} = {own, partner} in some order */
         auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
@@ -260,6 +317,83 @@ __device__ __forceinline__ int segment_min(int v)
     return v;
 }
 
+/* Pivot search of step k inside a segment: the segment maximum M of |a_rk|
+ * over candidate rows (pos >= k) is found with a VALU butterfly; a ballot of
+ * the lanes holding it gives the owner directly, and only when two lanes of
+ * some segment hold the same maximum (a tie, rare for non-integer data) does
+ * a second reduction pick the lowest position. Returns the owner's lane
+ * within the segment; lpos / ls are this lane's best candidate position and
+ * slot (meaningful in the owner). */
+template <int N, int T, int k>
+__device__ __forceinline__ int lanes_pivot_owner(const double (&a)[(N + T - 1) / T][N],
+                                                 const int (&pos)[(N + T - 1) / T], int seg_base,
+                                                 double &M, int &lpos, int &ls)
+{
+    constexpr int K = lanes_shape<N, T>::K;
+    const unsigned lowmask = T >= 32 ? 0xffffffffu : ((1u << (T & 31)) - 1u);
+    /* local candidate: largest |a_rk| among rows with pos >= k, lowest pos on ties */
+    double mag = -1.0;
+    lpos = 0x7fffffff;
+    ls = 0;
+    static_for<0, K>(LUPP_SF(sc) {
+        constexpr int s = decltype(sc)::value;
+        const double v = fabs(a[s][k]);
+        /* non-short-circuit logic: selects, not branches */
+        const bool take = (pos[s] >= k) & ((v > mag) | ((v == mag) & (pos[s] < lpos)));
+        mag = take ? v : mag;
+        lpos = take ? pos[s] : lpos;
+        ls = take ? s : ls;
+    });
+    M = segment_max<T>(mag);
+    const uint64_t hits = __ballot(mag == M);
+    const unsigned sb = (unsigned)(hits >> (unsigned)seg_base) & lowmask;
+    /* sb != 0 for finite data; lane 0 keeps the owner inside the segment
+     * otherwise (NaN entries, outside the solver's contract) */
+    int tp = sb ? (int)__builtin_ctz(sb) : 0;
+    if (__ballot(__builtin_popcount(sb) > 1) != 0) {
+        /* a tie between lanes in some segment: lowest position wins */
+        const int pmin = segment_min<T>(mag == M ? lpos : 0x7fffffff);
+        const unsigned s2 =
+            (unsigned)(__ballot(mag == M && lpos == pmin) >> (unsigned)seg_base) & lowmask;
+        tp = s2 ? (int)__builtin_ctz(s2) : tp;
+    }
+    /* a lane without candidate (only with NaN entries) reports the last row */
+    lpos = lpos < N ? lpos : N - 1;
+    return tp;
+}
+
+/* Back substitution, column j descending: x_j lives in the row at position j;
+ * its owner divides, broadcasts x_j, and the rows above eliminate it. */
+template <int N, int T>
+__device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) / T][N],
+                                                 double (&b)[(N + T - 1) / T],
+                                                 const int (&pos)[(N + T - 1) / T], int seg_base)
+{
+    constexpr int K = lanes_shape<N, T>::K;
+    const unsigned lowmask = T >= 32 ? 0xffffffffu : ((1u << (T & 31)) - 1u);
+    static_for_down<0, N>(LUPP_SF(jc) {
+        constexpr int j = decltype(jc)::value;
+        bool mine = false;
+        double bs = 0.0, us = 1.0;
+        static_for<0, K>(LUPP_SF(sc) {
+            constexpr int s = decltype(sc)::value;
+            const bool hit = pos[s] == j;
+            mine = mine || hit;
+            bs = hit ? b[s] : bs;
+            us = hit ? a[s][j] : us;
+        });
+        const double xl = bs / us;
+        const unsigned ob = (unsigned)(__ballot(mine) >> (unsigned)seg_base) & lowmask;
+        const int owner = seg_base + (int)__builtin_ctz(ob | (1u << 31));
+        const double x = bcast_f64(xl, owner);
+        static_for<0, K>(LUPP_SF(sc) {
+            constexpr int s = decltype(sc)::value;
+            if (pos[s] == j) b[s] = x;
+            else if (pos[s] >= 0 && pos[s] < j) b[s] = b[s] - a[s][j] * x;
+        });
+    });
+}
+
 /* Factor (and solve, on info == 0) the system owned by this segment.
  * a[s][j]: row t+s*T, column j; b[s]: its right-hand side entry; pos[s] must
  * be initialised to the row index (or -1 for a phantom row). On return
@@ -268,12 +402,9 @@ __device__ __forceinline__ int segment_min(int v)
  * wave lane of the segment's lane 0. ipiv_k(k, v) is called by every lane
  * with the segment-uniform interchange ipiv[k] = v (1-based).
  *
- * Pivot search: the segment maximum of |a_rk| over candidate rows (pos >= k)
- * is found with a VALU butterfly; a ballot of the lanes holding it gives the
- * owner directly, and only when two lanes of some segment hold the same
- * maximum (a tie, rare for non-integer data) does a second reduction pick
- * the lowest position. The trailing update runs under the exec mask of the
- * trailing rows (pos > k), with the pivot row broadcast beforehand. */
+ * The pivot row reaches the other lanes of the segment by ds_bpermute, and
+ * the trailing update runs under the exec mask of the trailing rows
+ * (pos > k). No LDS allocation is needed. */
 template <int N, int T, typename IpivSink>
 __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N],
                                                  double (&b)[(N + T - 1) / T],
@@ -283,32 +414,12 @@ __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N]
     constexpr int K = lanes_shape<N, T>::K;
     constexpr int CH = 8; /* pivot-row columns broadcast per chunk */
     const int lane_in_seg = (int)__lane_id() - seg_base;
-    const unsigned lowmask = T >= 32 ? 0xffffffffu : ((1u << T) - 1u);
     int info = 0;
     static_for<0, N>(LUPP_SF(kc) {
         constexpr int k = decltype(kc)::value;
-        /* local candidate: largest |a_rk| among rows with pos >= k, lowest pos on ties */
-        double mag = -1.0;
-        int lpos = 0x7fffffff, ls = 0;
-        static_for<0, K>(LUPP_SF(sc) {
-            constexpr int s = decltype(sc)::value;
-            const double v = fabs(a[s][k]);
-            const bool cand = pos[s] >= k;
-            const bool take = cand && ((v > mag) || (v == mag && pos[s] < lpos));
-            mag = take ? v : mag;
-            lpos = take ? pos[s] : lpos;
-            ls = take ? s : ls;
-        });
-        const double M = segment_max<T>(mag);
-        const uint64_t hits = __ballot(mag == M);
-        const unsigned sb = (unsigned)(hits >> (unsigned)seg_base) & lowmask;
-        int tp = (int)__builtin_ctz(sb | (1u << 31));
-        if (__ballot(__builtin_popcount(sb) > 1) != 0) {
-            /* a tie between lanes in some segment: lowest position wins */
-            const int pmin = segment_min<T>(mag == M ? lpos : 0x7fffffff);
-            const uint64_t h2 = __ballot(mag == M && lpos == pmin);
-            tp = (int)__builtin_ctz(((unsigned)(h2 >> (unsigned)seg_base) & lowmask) | (1u << 31));
-        }
+        double M;
+        int lpos, ls;
+        const int tp = lanes_pivot_owner<N, T, k>(a, pos, seg_base, M, lpos, ls);
         const int src = seg_base + tp;
         const int ql = bcast_i32((lpos << 8) | ls, src);
         const int q = ql >> 8;  /* current position of the pivot row */
@@ -376,30 +487,7 @@ __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N]
             }
         }
     });
-    if (info == 0) {
-        /* back substitution, column j descending: x_j lives in the row at position j */
-        static_for_down<0, N>(LUPP_SF(jc) {
-            constexpr int j = decltype(jc)::value;
-            bool mine = false;
-            double bs = 0.0, us = 1.0;
-            static_for<0, K>(LUPP_SF(sc) {
-                constexpr int s = decltype(sc)::value;
-                const bool hit = pos[s] == j;
-                mine = mine || hit;
-                bs = hit ? b[s] : bs;
-                us = hit ? a[s][j] : us;
-            });
-            const double xl = bs / us;
-            const unsigned ob = (unsigned)(__ballot(mine) >> (unsigned)seg_base) & lowmask;
-            const int owner = seg_base + (int)__builtin_ctz(ob | (1u << 31));
-            const double x = bcast_f64(xl, owner);
-            static_for<0, K>(LUPP_SF(sc) {
-                constexpr int s = decltype(sc)::value;
-                if (pos[s] == j) b[s] = x;
-                else if (pos[s] >= 0 && pos[s] < j) b[s] = b[s] - a[s][j] * x;
-            });
-        });
-    }
+    if (info == 0) lanes_back_subst<N, T>(a, b, pos, seg_base);
     return info;
 }
 

@@ -198,13 +198,20 @@ void oracle_gesv_ragged(int64_t batch, const int32_t *n, const int64_t *offA,
 /*            F_a = d_alpha - dp N + D dp alpha.                            */
 /* The Jacobian is the exact derivative of these residuals.                  */
 /* ------------------------------------------------------------------------ */
+/* Lame constants of the isotropic elastic stiffness. */
+static void oracle_lame(const oracle_law *law, double *lam, double *mu)
+{
+    *lam = law->E * law->nu / ((1.0 + law->nu) * (1.0 - 2.0 * law->nu));
+    *mu = law->E / (2.0 * (1.0 + law->nu));
+}
+
 void oracle_law_eval(const oracle_law *law, const double *deps, const double *state_t,
                      const double *y, double *F, double *J, double *sig)
 {
     const int nunk = law->kind;
     const int af = (law->kind == 13);
-    const double lam = law->E * law->nu / ((1.0 + law->nu) * (1.0 - 2.0 * law->nu));
-    const double mu = law->E / (2.0 * (1.0 + law->nu));
+    double lam, mu;
+    oracle_lame(law, &lam, &mu);
 
     double eel[6], s[6], xi[6], alpha[6], N[6];
     for (int i = 0; i < 6; ++i) eel[i] = state_t[i] + y[i];
@@ -273,9 +280,37 @@ void oracle_law_eval(const oracle_law *law, const double *deps, const double *st
  * increments; at each iterate evaluate F; stop on a non-finite residual, on
  * ||F||_inf < tol, or after maxit linear solves; otherwise factor J with
  * partial pivoting, solve J dx = -F and update x += dx. */
+/* Consistent tangent operator at a converged point (Section 2.5: the
+ * consistent linearisation of the implicit update; Section 4.3: one
+ * multi-right-hand-side solve after convergence). With F(y; deps) = 0 at the
+ * converged unknowns y and dF/d(deps) = -[I6; 0], the sensitivity is
+ * dy/d(deps) = J^-1 [I6; 0]: factor the Jacobian J of the converged iterate
+ * with partial pivoting and solve for the six unit right-hand sides. The
+ * stress sig = D (eel_t + d_eel) then gives dsig/d(deps) = D X_e, X_e the
+ * first six rows of the solution. Output row-major: tan[6*r + c] =
+ * dsig_r / d(deps)_c. A singular J gives NaN entries. */
+static void oracle_tangent(const oracle_law *law, double *J, double *tan)
+{
+    const int nunk = law->kind;
+    double lam, mu;
+    oracle_lame(law, &lam, &mu);
+    int32_t piv[13];
+    if (oracle_getrf(nunk, J, nunk, piv, NULL) != 0) {
+        for (int i = 0; i < 36; ++i) tan[i] = NAN;
+        return;
+    }
+    for (int c = 0; c < 6; ++c) {
+        double x[13];
+        for (int i = 0; i < nunk; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+        oracle_getrs(nunk, J, nunk, piv, x);
+        const double tr = x[0] + x[1] + x[2];
+        for (int r = 0; r < 6; ++r) tan[6 * r + c] = 2.0 * mu * x[r] + (r < 3 ? lam * tr : 0.0);
+    }
+}
+
 static void oracle_newton_point(const oracle_law *law, const double *deps, double *state,
                                 double *sig, int32_t *iters, int32_t *status, double *resid,
-                                double tol, int maxit)
+                                double *tan, double tol, int maxit)
 {
     const int nunk = law->kind;
     double y[13], F[13], J[169], dx[13];
@@ -314,6 +349,8 @@ static void oracle_newton_point(const oracle_law *law, const double *deps, doubl
     *iters = k;
     *status = st;
     *resid = nrm;
+    /* J holds the (unfactored) Jacobian of the converged iterate */
+    if (st == 0 && tan != NULL) oracle_tangent(law, J, tan);
     if (st == 0)
         for (int i = 0; i < nunk; ++i) state[i] = state[i] + y[i];
 }
@@ -321,7 +358,7 @@ static void oracle_newton_point(const oracle_law *law, const double *deps, doubl
 typedef struct {
     const oracle_law *law;
     const double *deps;
-    double *state, *sig, *resid;
+    double *state, *sig, *resid, *tan;
     int32_t *iters, *status;
     double tol;
     int maxit;
@@ -333,14 +370,15 @@ static void newton_body(void *p, int64_t lo, int64_t hi)
     const int nunk = c->law->kind;
     for (int64_t s = lo; s < hi; ++s)
         oracle_newton_point(c->law, c->deps + 6 * s, c->state + nunk * s, c->sig + 6 * s,
-                            c->iters + s, c->status + s, c->resid + s, c->tol, c->maxit);
+                            c->iters + s, c->status + s, c->resid + s,
+                            c->tan ? c->tan + 36 * s : NULL, c->tol, c->maxit);
 }
 
 void oracle_constitutive_update(const oracle_law *law, int64_t count, const double *deps,
                                 double *state, double *sig, int32_t *iters,
-                                int32_t *status, double *resid, double tol, int maxit,
-                                int nthreads)
+                                int32_t *status, double *resid, double *tangent, double tol,
+                                int maxit, int nthreads)
 {
-    newton_ctx c = {law, deps, state, sig, resid, iters, status, tol, maxit};
+    newton_ctx c = {law, deps, state, sig, resid, tangent, iters, status, tol, maxit};
     oracle_parallel_for(count, nthreads, newton_body, &c);
 }

@@ -79,11 +79,14 @@ void oracle_law_eval(const oracle_law *law, const double *deps, const double *st
  * where status == 0), sig[count][6], iters/status[count], resid[count] = the
  * infinity norm of the residual that decided the stop (NAN if non-finite).
  * status: 0 converged, 1 maxit reached, 2 singular Jacobian, 3 non-finite
- * residual. */
+ * residual. tangent: NULL, or [count][36] receiving the consistent tangent
+ * dsig/d(deps) (row-major 6x6, Kelvin) of every converged point (Section
+ * 2.5; Section 4.3: a multi-right-hand-side solve with the factors of the
+ * Jacobian at the converged iterate); other points' entries are untouched. */
 void oracle_constitutive_update(const oracle_law *law, int64_t count, const double *deps,
                                 double *state, double *sig, int32_t *iters,
-                                int32_t *status, double *resid, double tol, int maxit,
-                                int nthreads);
+                                int32_t *status, double *resid, double *tangent, double tol,
+                                int maxit, int nthreads);
 
 #ifdef __cplusplus
 }

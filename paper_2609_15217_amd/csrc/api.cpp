@@ -261,7 +261,10 @@ int lupp_autotune(lupp_ctx *ctx, int n, int64_t batch, int layout, const double 
     int nc = 0;
     for (int w = 1; w <= 4; w <<= 1) {
         if (thread_launcher(n) != nullptr) cands[nc++] = {LUPP_VARIANT_THREAD, 1, w};
-        for (int i = 0; i < nw; ++i) cands[nc++] = {LUPP_VARIANT_LANES, widths[i], w};
+        /* the SoA lanes kernel has one workgroup shape */
+        if (layout == LUPP_SOA && w > 1) continue;
+        for (int i = 0; i < nw; ++i)
+            cands[nc++] = {LUPP_VARIANT_LANES, widths[i], layout == LUPP_SOA ? 0 : w};
     }
     SolveArgs a{batch, wA, lda, strideA, wB, strideB, wP, wI};
     for (int c = 0; c < nc && rc == 0; ++c) {
@@ -310,13 +313,12 @@ int lupp_autotune(lupp_ctx *ctx, int n, int64_t batch, int layout, const double 
 int lupp_variant_info(int n, int layout, int variant, int lanes, int keep_a,
                       lupp_kernel_info *out)
 {
-    (void)keep_a;
     if (out == nullptr) return -6;
     const void *sym = nullptr;
     if (variant == LUPP_VARIANT_THREAD) sym = thread_kernel_symbol(n);
     else if (variant == LUPP_VARIANT_LANES) sym = lanes_kernel_symbol(n, lanes, layout);
     else if (variant == 100 + LUPP_LAW_NORTON7 || variant == 100 + LUPP_LAW_NORTON_AF13)
-        sym = constitutive_kernel_symbol(variant - 100);
+        sym = constitutive_kernel_symbol(variant - 100, keep_a != 0);
     if (sym == nullptr) return LUPP_E_UNSUPPORTED;
     hipFuncAttributes fa;
     std::memset(&fa, 0, sizeof(fa));

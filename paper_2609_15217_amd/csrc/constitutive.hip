@@ -108,9 +108,77 @@ __device__ __forceinline__ void law_assemble(const LawK &P, const double (&de)[6
     }
 }
 
+/* Consistent tangent (Section 2.5; Section 4.3: one multi-right-hand-side
+ * solve after convergence) at the converged unknowns y: with dF/d(deps) =
+ * -[I6; 0], dy/d(deps) = J^-1 [I6; 0] for the Jacobian J of the converged
+ * iterate, and dsig/d(deps) = D dy_e/d(deps). Column c of the result needs
+ * J^-1 e_c: LU with partial pivoting, then the interchanges and the forward
+ * and back substitutions applied to e_c. Column c is stored at tangent
+ * components 6 r + c, r = 0..5. */
 template <int NU>
+__device__ __forceinline__ void tangent_store_col(const LawK &P, const lupp_points &pts, int64_t p0,
+                                                  uint32_t nb, uint32_t vo, int c,
+                                                  const double (&x)[NU], bool sing)
+{
+    const double lt = P.lam * (x[0] + x[1] + x[2]);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        const double t = P.two_mu * x[r] + (r < 3 ? lt : 0.0);
+        const auto rt = make_rsrc(pts.tangent + (6 * r + c) * pts.ld + p0, nb);
+        buf_store_f64(rt, vo, 0, sing ? __builtin_nan("") : t);
+    }
+}
+
+/* 7 unknowns: J is factored once and the six unit vectors are solved with
+ * the kept factors (all of it fits in registers next to the Newton loop). */
+__device__ __forceinline__ void newton_tangent7(const LawK &P, const double (&de)[6],
+                                                const double (&st)[7], const double (&y)[7],
+                                                const lupp_points &pts, int64_t p0, uint32_t nb,
+                                                uint32_t vo)
+{
+    double J[7][7], Fc[7], sc[6], z[7];
+    int piv[7], perm[7];
+    law_assemble<7>(P, de, st, y, Fc, J, sc);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) z[i] = 0.0;
+    const bool sing = thread_getrf_solve<7, true>(J, z, piv) != 0;
+    thread_ipiv_to_perm<7>(piv, perm);
+#pragma unroll 1
+    for (int c = 0; c < 6; ++c) {
+        double x[7];
+        thread_solve_unit<7>(J, perm, c, x);
+        tangent_store_col<7>(P, pts, p0, nb, vo, c, x, sing);
+    }
+}
+
+/* 13 unknowns: the 13 x 13 factors and a solution vector do not fit in
+ * registers together, so each column re-assembles J and runs the fused
+ * factor-and-solve on e_c. Every column sees the same factorization and the
+ * same operation sequence, so the result is bitwise that of the factor-once
+ * form. Not inlined: it gets its own register budget instead of adding to
+ * the Newton loop's. */
+__device__ __attribute__((noinline)) void newton_tangent13(const LawK &P, const double (&de)[6],
+                                                           const double (&st)[13],
+                                                           const double (&y)[13],
+                                                           const lupp_points &pts, int64_t p0,
+                                                           uint32_t nb, uint32_t vo)
+{
+#pragma unroll 1
+    for (int c = 0; c < 6; ++c) {
+        double J[13][13], Fc[13], sc[6], x[13];
+        int piv[13];
+        law_assemble<13>(P, de, st, y, Fc, J, sc);
+#pragma unroll
+        for (int i = 0; i < 13; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+        const bool sing = thread_getrf_solve<13, false>(J, x, piv) != 0;
+        tangent_store_col<13>(P, pts, p0, nb, vo, c, x, sing);
+    }
+}
+
+template <int NU, bool TAN>
 __global__ void __launch_bounds__(256) k_newton(lupp_points pts, LawK P, double tol, int maxit)
 {
+    constexpr bool kTangent = TAN;
     const int64_t p0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
     const int64_t rem = pts.count - p0;
     const uint32_t nvalid = (uint32_t)(rem < (int64_t)blockDim.x ? rem : blockDim.x);
@@ -157,6 +225,13 @@ __global__ void __launch_bounds__(256) k_newton(lupp_points pts, LawK P, double 
         buf_store_f64(make_rsrc(pts.state + c * pts.ld + p0, nb), vs, 0, st[c] + y[c]);
     buf_store_i32(make_rsrc(pts.iters + p0, nvalid * 4u), tid * 4u, 0, it);
     buf_store_i32(make_rsrc(pts.status + p0, nvalid * 4u), tid * 4u, 0, status);
+
+    if constexpr (kTangent) {
+        if (status == 0) {
+            if constexpr (NU == 7) newton_tangent7(P, de, st, y, pts, p0, nb, vo);
+            else newton_tangent13(P, de, st, y, pts, p0, nb, vo);
+        }
+    }
 }
 
 static LawK law_constants(const lupp_law *law)
@@ -177,19 +252,26 @@ int constitutive_launch(const lupp_points *pts, const lupp_law *law, double tol,
     const LawK P = law_constants(law);
     const int threads = 256;
     const int64_t blocks = (pts->count + threads - 1) / threads;
-    if (law->kind == LUPP_LAW_NORTON7)
-        hipLaunchKernelGGL((k_newton<7>), dim3((unsigned)blocks), dim3(threads), 0, stream, *pts, P,
-                           tol, maxit);
-    else
-        hipLaunchKernelGGL((k_newton<13>), dim3((unsigned)blocks), dim3(threads), 0, stream, *pts,
-                           P, tol, maxit);
+    const bool tan = pts->tangent != nullptr;
+    const dim3 g((unsigned)blocks), b(threads);
+    if (law->kind == LUPP_LAW_NORTON7) {
+        if (tan) hipLaunchKernelGGL((k_newton<7, true>), g, b, 0, stream, *pts, P, tol, maxit);
+        else hipLaunchKernelGGL((k_newton<7, false>), g, b, 0, stream, *pts, P, tol, maxit);
+    } else {
+        if (tan) hipLaunchKernelGGL((k_newton<13, true>), g, b, 0, stream, *pts, P, tol, maxit);
+        else hipLaunchKernelGGL((k_newton<13, false>), g, b, 0, stream, *pts, P, tol, maxit);
+    }
     return hip_err(hipGetLastError());
 }
 
-const void *constitutive_kernel_symbol(int kind)
+const void *constitutive_kernel_symbol(int kind, bool tangent)
 {
-    if (kind == LUPP_LAW_NORTON7) return reinterpret_cast<const void *>(&k_newton<7>);
-    if (kind == LUPP_LAW_NORTON_AF13) return reinterpret_cast<const void *>(&k_newton<13>);
+    if (kind == LUPP_LAW_NORTON7)
+        return tangent ? reinterpret_cast<const void *>(&k_newton<7, true>)
+                       : reinterpret_cast<const void *>(&k_newton<7, false>);
+    if (kind == LUPP_LAW_NORTON_AF13)
+        return tangent ? reinterpret_cast<const void *>(&k_newton<13, true>)
+                       : reinterpret_cast<const void *>(&k_newton<13, false>);
     return nullptr;
 }
 

@@ -43,7 +43,7 @@ constexpr int kThreadMaxN = 13;
 /* Constitutive update launcher (constitutive.hip). */
 int constitutive_launch(const lupp_points *pts, const lupp_law *law, double tol, int maxit,
                         hipStream_t stream);
-const void *constitutive_kernel_symbol(int kind);
+const void *constitutive_kernel_symbol(int kind, bool tangent);
 
 /* Ragged batch (ragged.hip): device workspace owned by a context. */
 struct RaggedWs;

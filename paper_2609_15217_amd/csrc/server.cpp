@@ -108,7 +108,7 @@ static size_t footprint(const lupp_request &r)
                round256(B * 4);
     }
     const size_t P = (size_t)r.count;
-    return round256(P * 6 * 8) * 2 + round256(P * 4) * 2;
+    return round256(P * 6 * 8) * 2 + round256(P * 4) * 2 + (r.tangent ? round256(P * 36 * 8) : 0);
 }
 
 }  // namespace lupp
@@ -206,15 +206,20 @@ static int launch_req(lupp_server *s, Req *q, double *set_state)
         double *dsig = reinterpret_cast<double *>(base + round256(P * 48));
         int32_t *dit = reinterpret_cast<int32_t *>(base + 2 * round256(P * 48));
         int32_t *dst = reinterpret_cast<int32_t *>(base + 2 * round256(P * 48) + round256(P * 4));
+        double *dtan = r.tangent ? reinterpret_cast<double *>(base + 2 * round256(P * 48) +
+                                                              2 * round256(P * 4))
+                                 : nullptr;
         e = hipMemcpyAsync(dd, r.deps, P * 48, kind_of(r.deps), st);
         if (e != hipSuccess) return hip_err(e);
-        lupp_points pts{(int64_t)P, (int64_t)P, dd, set_state, dsig, dit, dst};
+        lupp_points pts{(int64_t)P, (int64_t)P, dd, set_state, dsig, dit, dst, dtan};
         rc = constitutive_update(s->ctx, &pts, &q->law, r.tol, r.maxit, st);
         if (rc != 0) return rc;
         if (r.sig) e = hipMemcpyAsync(r.sig, dsig, P * 48, kind_out(r.sig), st);
         if (e == hipSuccess && r.iters) e = hipMemcpyAsync(r.iters, dit, P * 4, kind_out(r.iters), st);
         if (e == hipSuccess && r.status)
             e = hipMemcpyAsync(r.status, dst, P * 4, kind_out(r.status), st);
+        if (e == hipSuccess && r.tangent)
+            e = hipMemcpyAsync(r.tangent, dtan, P * 36 * 8, kind_out(r.tangent), st);
     }
     return hip_err(e);
 }

@@ -43,7 +43,7 @@ class lupp_law(ctypes.Structure):
 
 class lupp_points(ctypes.Structure):
     _fields_ = [("count", _i64), ("ld", _i64), ("deps", _P), ("state", _P), ("sig", _P),
-                ("iters", _P), ("status", _P)]
+                ("iters", _P), ("status", _P), ("tangent", _P)]
 
 
 class lupp_kernel_info(ctypes.Structure):
@@ -97,7 +97,8 @@ class lupp_request(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("n", ctypes.c_int), ("batch", _i64), ("A", _P), ("b", _P),
                 ("x", _P), ("ipiv", _P), ("info", _P), ("lu", _P), ("set_id", _i64),
                 ("count", _i64), ("law", ctypes.POINTER(lupp_law)), ("tol", ctypes.c_double),
-                ("maxit", ctypes.c_int), ("deps", _P), ("sig", _P), ("iters", _P), ("status", _P)]
+                ("maxit", ctypes.c_int), ("deps", _P), ("sig", _P), ("iters", _P), ("status", _P),
+                ("tangent", _P)]
 
 
 class lupp_server_stats(ctypes.Structure):
@@ -128,7 +129,8 @@ EXPORTED = ["lupp_create", "lupp_destroy", "lupp_batched_solve", "lupp_batched_s
             "lupp_autotune", "lupp_get_device", "lupp_server_create", "lupp_server_destroy",
             "lupp_server_add_points", "lupp_server_read_points", "lupp_server_submit",
             "lupp_server_poll", "lupp_server_wait", "lupp_server_get_stats",
-            "lupp_server_reset_stats"]
+            "lupp_server_reset_stats", "lupp_sweep_create", "lupp_sweep_launch",
+            "lupp_sweep_destroy"]
 
 
 class LuppError(RuntimeError):
@@ -257,6 +259,54 @@ def constitutive_update(ctx: Context, pts: lupp_points, law: lupp_law, tol: floa
 
 
 # --------------------------------------------------------------------------
+# Time-step sweeps captured in a HIP graph
+# --------------------------------------------------------------------------
+_lupp_sweep_create = _sig("lupp_sweep_create", ctypes.c_int,
+                          [_P, ctypes.POINTER(lupp_points), ctypes.POINTER(lupp_law),
+                           ctypes.c_double, ctypes.c_int, ctypes.c_int, _i64, ctypes.POINTER(_P)])
+_lupp_sweep_launch = _sig("lupp_sweep_launch", ctypes.c_int, [_P, _P])
+_lupp_sweep_destroy = _sig("lupp_sweep_destroy", None, [_P])
+
+
+class Sweep:
+    """Owns a lupp_sweep (an instantiated HIP graph of `steps` updates)."""
+
+    def __init__(self, ctx: Context, pts: lupp_points, law: lupp_law, tol: float, maxit: int,
+                 steps: int, deps_step: int):
+        h = _P()
+        _check(_lupp_sweep_create(ctx.handle, ctypes.byref(pts), ctypes.byref(law), tol, maxit,
+                                  steps, deps_step, ctypes.byref(h)), "lupp_sweep_create")
+        self.handle = h
+
+    def launch(self, stream=None) -> int:
+        return _lupp_sweep_launch(self.handle, _stream(stream))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _lupp_sweep_destroy(self.handle)
+            self.handle = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lupp_sweep_create(ctx: Context, pts: lupp_points, law: lupp_law, tol: float, maxit: int,
+                      steps: int, deps_step: int) -> Sweep:
+    return Sweep(ctx, pts, law, tol, maxit, steps, deps_step)
+
+
+def lupp_sweep_launch(sweep: Sweep, stream=None) -> int:
+    return sweep.launch(stream)
+
+
+def lupp_sweep_destroy(sweep: Sweep):
+    sweep.close()
+
+
+# --------------------------------------------------------------------------
 # Tensor-level helpers (marshalling only)
 # --------------------------------------------------------------------------
 def batched_solve(ctx: Context, A: torch.Tensor, b: torch.Tensor, layout: int = LUPP_AOS,
@@ -291,15 +341,17 @@ def make_law(kind: int = 7, E=200e3, nu=0.3, A=1e-8, m=5.0, C=1e4, D=100.0, dt=1
 
 
 def points(deps: torch.Tensor, state: torch.Tensor, sig: torch.Tensor, iters: torch.Tensor,
-           status: torch.Tensor) -> lupp_points:
+           status: torch.Tensor, tangent: torch.Tensor | None = None) -> lupp_points:
     """SoA point buffers: deps (6, ld), state (kind, ld), sig (6, ld),
-    iters/status (count,) int32."""
+    iters/status (count,) int32, optional tangent (36, ld)."""
     count = iters.shape[0]
     ld = deps.shape[1]
-    for t in (deps, state, sig):
+    bufs = (deps, state, sig) if tangent is None else (deps, state, sig, tangent)
+    for t in bufs:
         assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.shape[1] == ld
     return lupp_points(count, ld, deps.data_ptr(), state.data_ptr(), sig.data_ptr(),
-                       iters.data_ptr(), status.data_ptr())
+                       iters.data_ptr(), status.data_ptr(),
+                       None if tangent is None else tangent.data_ptr())
 
 
 # --------------------------------------------------------------------------
@@ -364,15 +416,14 @@ def solve_request(n: int, batch: int, A, b, x, ipiv=None, info=None, lu=None) ->
 
 
 def update_request(set_id: int, count: int, law: lupp_law, deps, sig=None, iters=None, status=None,
-                   tol: float = 1e-12, maxit: int = 20) -> lupp_request:
+                   tol: float = 1e-12, maxit: int = 20, tangent=None) -> lupp_request:
     r = lupp_request()
     r.kind, r.set_id, r.count = LUPP_REQ_UPDATE, set_id, count
     r.law = ctypes.pointer(law)
     r.tol, r.maxit = tol, maxit
     r.deps, r.sig, r.iters, r.status = _ptr(deps), _ptr(sig), _ptr(iters), _ptr(status)
+    r.tangent = _ptr(tangent)
     return r
-
-
 
 
 def lupp_server_submit(server: Server, req: lupp_request) -> int:

@@ -29,7 +29,7 @@ def ctx(L):
     return L.Context(0)
 
 
-def gpu_update(L, ctx, law: Law, deps, state=None, tol=1e-12, maxit=20, pad=0):
+def gpu_update(L, ctx, law: Law, deps, state=None, tol=1e-12, maxit=20, pad=0, tangent=False):
     count = deps.shape[0]
     ld = count + pad
     dev = torch.device("cuda:0")
@@ -41,14 +41,19 @@ def gpu_update(L, ctx, law: Law, deps, state=None, tol=1e-12, maxit=20, pad=0):
     sig = torch.full((6, ld), np.nan, dtype=torch.float64, device=dev)
     iters = torch.full((count,), -1, dtype=torch.int32, device=dev)
     status = torch.full((count,), -1, dtype=torch.int32, device=dev)
-    pts = L.points(d, st, sig, iters, status)
+    tan = torch.full((36, ld), np.nan, dtype=torch.float64, device=dev) if tangent else None
+    pts = L.points(d, st, sig, iters, status, tan)
     lw = L.make_law(law.kind, law.E, law.nu, law.A, law.m, law.C, law.D, law.dt)
     rc = L.constitutive_update(ctx, pts, lw, tol, maxit)
     assert rc == 0, L.lupp_error_string(rc)
     torch.cuda.synchronize()
-    return {"sig": sig[:, :count].cpu().numpy().T, "state": st[:, :count].cpu().numpy().T,
-            "iters": iters.cpu().numpy(), "status": status.cpu().numpy(),
-            "pad_sig": sig[:, count:].cpu().numpy(), "pad_state": st[:, count:].cpu().numpy()}
+    out = {"sig": sig[:, :count].cpu().numpy().T, "state": st[:, :count].cpu().numpy().T,
+           "iters": iters.cpu().numpy(), "status": status.cpu().numpy(),
+           "pad_sig": sig[:, count:].cpu().numpy(), "pad_state": st[:, count:].cpu().numpy()}
+    if tangent:
+        out["tangent"] = tan[:, :count].cpu().numpy().T.reshape(count, 6, 6)
+        out["pad_tangent"] = tan[:, count:].cpu().numpy()
+    return out
 
 
 def compare(o, g, rel=1e-10, min_agree=0.999):
@@ -65,6 +70,7 @@ def compare(o, g, rel=1e-10, min_agree=0.999):
     assert (np.abs(st_o - st_g).max(axis=1) / scale).max() <= rel
     bad = o["status"] != 0
     assert np.array_equal(o["state"][bad], g["state"][bad])  # not committed
+    return ok
 
 
 @pytest.mark.parametrize("kind", [7, 13])
@@ -149,3 +155,38 @@ def test_full_size_sampled(L, ctx, kind):
     o = oracle.constitutive_update(law, deps[idx], threads=8)
     compare(o, {k: v[idx] for k, v in g.items() if not k.startswith("pad")})
     assert (g["status"] == 0).mean() > 0.999
+
+
+@pytest.mark.parametrize("kind", [7, 13])
+def test_consistent_tangent_matches_oracle(L, ctx, kind):
+    """Consistent tangent (Section 4.3: a multi-right-hand-side solve after
+    convergence): same points converged, tangents within 1e-9 relative where
+    status and iterations agree; untouched for unconverged points and in the
+    padding; the stress and state are those of the update without tangent."""
+    law = Law(kind=kind)
+    deps = newton_points(3000, seed=60 + kind)
+    o = oracle.constitutive_update(law, deps, maxit=16, threads=8, tangent=True)
+    g = gpu_update(L, ctx, law, deps, maxit=16, pad=7, tangent=True)
+    ok = compare(o, g, min_agree=0.99)
+    conv = g["status"] == 0
+    assert conv.mean() > 0.05 and (~conv).any()  # both kinds of points present
+    T_o, T_g = o["tangent"][ok], g["tangent"][ok]
+    rel = np.abs(T_o - T_g).max(axis=(1, 2)) / np.abs(T_o).max(axis=(1, 2))
+    assert rel.max() <= 1e-9, rel.max()
+    assert np.all(np.isnan(g["tangent"][~conv]))
+    assert np.all(np.isnan(g["pad_tangent"]))
+    plain = gpu_update(L, ctx, law, deps, maxit=16)
+    assert np.array_equal(plain["sig"], g["sig"]) and np.array_equal(plain["state"], g["state"])
+    assert np.array_equal(plain["iters"], g["iters"])
+
+
+def test_tangent_elastic_limit(L, ctx):
+    law = Law(kind=13, A=0.0)
+    deps = newton_points(500, seed=65)
+    g = gpu_update(L, ctx, law, deps, tangent=True)
+    lam = law.E * law.nu / ((1 + law.nu) * (1 - 2 * law.nu))
+    mu = law.E / (2 * (1 + law.nu))
+    one = np.array([1, 1, 1, 0, 0, 0.0])
+    D = lam * np.outer(one, one) + 2 * mu * np.eye(6)
+    assert np.all(g["status"] == 0)
+    assert np.abs(g["tangent"] - D).max() <= 1e-12 * np.abs(D).max()

@@ -29,8 +29,10 @@ MUTANTS = {
     "von_mises_factor": ("double seq = sqrt(1.5 * xx);", "double seq = sqrt(xx);"),
     "jacobian_drops_dFp_deel": ("JAC(6, a) = -gdot * 2.0 * mu * KN[a];", "JAC(6, a) = 0.0;"),
     "af_recall_sign": ("+ law->D * dp * alpha[i];", "- law->D * dp * alpha[i];"),
-    "lame_mu": ("const double mu = law->E / (2.0 * (1.0 + law->nu));",
-                "const double mu = law->E / (1.0 + law->nu);"),
+    "lame_mu": ("*mu = law->E / (2.0 * (1.0 + law->nu));", "*mu = law->E / (1.0 + law->nu);"),
+    "tangent_transposed": ("tan[6 * r + c] =", "tan[6 * c + r] ="),
+    "tangent_drops_lambda": ("(r < 3 ? lam * tr : 0.0)", "0.0"),
+    "tangent_wrong_rhs": ("x[i] = (i == c) ? 1.0 : 0.0;", "x[i] = (i == c + 1) ? 1.0 : 0.0;"),
 }
 
 

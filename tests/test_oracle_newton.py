@@ -235,3 +235,99 @@ def test_iteration_statistics_reported(kind):
     out = oracle.constitutive_update(Law(kind=kind), deps, threads=8)
     assert (out["status"] == 0).mean() > 0.99
     assert 5 < out["iters"].mean() < 20
+
+
+# --------------------------------------------------------------------------
+# Consistent tangent operator dsig/d(deps) at convergence (Section 2.5;
+# Section 4.3: one multi-right-hand-side solve after convergence).
+# --------------------------------------------------------------------------
+
+def test_tangent_elastic_limit_is_the_stiffness():
+    law = Law(kind=7, A=0.0)
+    deps = newton_points(20, seed=31)
+    out = oracle.constitutive_update(law, deps, threads=1, tangent=True)
+    D = stiffness(law)
+    assert np.all(out["status"] == 0)
+    assert np.abs(out["tangent"] - D).max() <= 1e-12 * np.abs(D).max()
+
+
+def prior_state(kind, count, seed):
+    """A non-virgin state: elastic strain and (AF) a back-strain alpha."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    st = np.zeros((count, kind))
+    st[:, :6] = rng.uniform(-1e-3, 1e-3, (count, 6))
+    if kind == 13:
+        st[:, 7:] = rng.uniform(-5e-3, 5e-3, (count, 6))
+    return st
+
+
+@pytest.mark.parametrize("virgin", [True, False])
+@pytest.mark.parametrize("kind", [7, 13])
+def test_tangent_matches_finite_differences_of_the_update(kind, virgin):
+    """Central differences of the converged stress over the strain increment
+    (each perturbed update converged to 1e-15) against the tangent. With a
+    back-strain the AF tangent is not symmetric, so a transposed tangent
+    fails here."""
+    law = Law(kind=kind)
+    deps = newton_points(12, seed=32 + kind)
+    st0 = None if virgin else prior_state(kind, 12, 35 + kind)
+    base = oracle.constitutive_update(law, deps, st0, tol=1e-15, maxit=80, threads=4,
+                                      tangent=True)
+    ok = base["status"] == 0  # (a few AF points do not converge from a loaded state)
+    assert ok.sum() >= 8
+    assert np.all(base["state"][ok, 6] > (0 if virgin else st0[ok, 6]))  # plastic flow
+    h = 1e-8
+    fd = np.zeros((12, 6, 6))
+    for c in range(6):
+        dp, dm = deps.copy(), deps.copy()
+        dp[:, c] += h
+        dm[:, c] -= h
+        sp = oracle.constitutive_update(law, dp, st0, tol=1e-15, maxit=80, threads=4)
+        sm = oracle.constitutive_update(law, dm, st0, tol=1e-15, maxit=80, threads=4)
+        assert np.all(sp["status"][ok] == 0) and np.all(sm["status"][ok] == 0)
+        fd[:, :, c] = (sp["sig"] - sm["sig"]) / (2 * h)
+    T, fd = base["tangent"][ok], fd[ok]
+    scale = np.abs(T).max(axis=(1, 2))
+    err = np.abs(T - fd).max(axis=(1, 2)) / scale
+    assert err.max() <= 1e-5, err
+    # viscoplastic flow makes the tangent softer than the elastic stiffness
+    D = stiffness(law)
+    assert np.all(np.abs(T - D).max(axis=(1, 2)) > 1e-3 * np.abs(D).max())
+
+
+@pytest.mark.parametrize("kind", [7, 13])
+def test_tangent_objectivity(kind):
+    """Virgin state, isotropic law: T(R deps) = R T(deps) R^T."""
+    rng = np.random.Generator(np.random.PCG64(40 + kind))
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    R = kelvin_rotation(Q)
+    deps = newton_points(50, seed=41)
+    law = Law(kind=kind)
+    o1 = oracle.constitutive_update(law, deps, tol=1e-15, maxit=80, threads=4, tangent=True)
+    o2 = oracle.constitutive_update(law, deps @ R.T, tol=1e-15, maxit=80, threads=4, tangent=True)
+    assert np.all(o1["status"] == 0) and np.all(o2["status"] == 0)
+    rot = R @ o1["tangent"] @ R.T
+    rel = np.abs(rot - o2["tangent"]).max(axis=(1, 2)) / np.abs(rot).max(axis=(1, 2))
+    assert rel.max() <= 1e-9
+
+
+def test_tangent_only_for_converged_points():
+    deps = newton_points(400, seed=42)
+    out = oracle.constitutive_update(Law(kind=7), deps, maxit=16, threads=2, tangent=True)
+    bad = out["status"] != 0
+    assert bad.any() and (~bad).any()
+    assert np.all(np.isnan(out["tangent"][bad]))
+    assert np.all(np.isfinite(out["tangent"][~bad]))
+
+
+def test_norton_tangent_is_symmetric():
+    """Associative J2 viscoplasticity integrated by backward Euler has a
+    symmetric consistent tangent (Kelvin notation), in any state."""
+    law = Law(kind=7)
+    deps = newton_points(40, seed=43)
+    o = oracle.constitutive_update(law, deps, prior_state(7, 40, 44), tol=1e-14, maxit=80,
+                                   threads=4, tangent=True)
+    T = o["tangent"][o["status"] == 0]
+    assert len(T) > 30
+    asym = np.abs(T - T.transpose(0, 2, 1)).max(axis=(1, 2)) / np.abs(T).max(axis=(1, 2))
+    assert asym.max() <= 1e-12
