@@ -56,12 +56,22 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# the sources the standalone-solve kernels are compiled from, the dispatch
+# table that picks them and the compile flags: counters taken on other
+# sources do not describe the kernels this run launches
+KERNEL_SOURCES = ("include/lupp.h", "include/lupp_device.h",
+                  "paper_2609_15217_amd/csrc/internal.h",
+                  "paper_2609_15217_amd/csrc/kernels_thread.h",
+                  "paper_2609_15217_amd/csrc/kernels_lanes.h",
+                  "paper_2609_15217_amd/csrc/kernels_lanes_soa.h",
+                  "paper_2609_15217_amd/dispatch_gfx950.json")
+
+
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for d in ("include", os.path.join("paper_2609_15217_amd", "csrc")):
-        p = os.path.join(ROOT, d)
-        for name in sorted(os.listdir(p)):
-            h.update(open(os.path.join(p, name), "rb").read())
+    from paper_2609_15217_amd.build import CXXFLAGS
+    h = hashlib.sha256(" ".join(f for f in CXXFLAGS if not f.startswith("/")).encode())
+    for rel in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -461,15 +471,35 @@ def main():
                 if r >= args.warmup:
                     ttimes.append(e0.elapsed_time(e1))
             tms = float(np.mean(ttimes))
+            # the CPU-driven batched form (Algorithm 1) of the same update
+            bt = {}
+            for name, flags in (("batched", 0), ("batched_graph", L.LUPP_BATCHED_GRAPH)):
+                times_b = []
+                for r in range(args.warmup + min(args.steps, 3)):
+                    st.zero_()
+                    torch.cuda.synchronize()
+                    t_s = time.perf_counter()
+                    rc, host_iters = L.constitutive_update_batched(ctx, pts, law, 1e-12, 20, flags,
+                                                                   stream)
+                    torch.cuda.synchronize()
+                    assert rc == 0
+                    if r >= args.warmup:
+                        times_b.append(time.perf_counter() - t_s)
+                bt[name] = (float(np.median(times_b)) * 1e3, host_iters)
             newton[f"norton{kind}"] = {"points": count, "ms": round(ms, 3),
                                        "updates_per_s": round(count / (ms * 1e-3)),
                                        "newton_iterations_per_s": round(its / (ms * 1e-3)),
                                        "mean_solves_per_point": round(its / count, 3),
                                        "converged": conv,
                                        "with_tangent_ms": round(tms, 3),
-                                       "with_tangent_updates_per_s": round(count / (tms * 1e-3))}
+                                       "with_tangent_updates_per_s": round(count / (tms * 1e-3)),
+                                       "batched_cpu_driven_ms": round(bt["batched"][0], 3),
+                                       "batched_graph_ms": round(bt["batched_graph"][0], 3),
+                                       "batched_host_iterations": bt["batched"][1],
+                                       "fused_speedup_vs_batched": round(bt["batched"][0] / ms, 2)}
             del tan
-            log(f"newton {kind}: {ms:.2f} ms, with tangent {tms:.2f} ms")
+            log(f"newton {kind}: {ms:.2f} ms, with tangent {tms:.2f} ms, batched "
+                f"{bt['batched'][0]:.2f} ms, batched graph {bt['batched_graph'][0]:.2f} ms")
 
     # ------------------------------------------------------------- sweeps
     sweep = {}

@@ -214,6 +214,26 @@ typedef struct {
 int constitutive_update(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law, double tol,
                         int maxit, void *stream);
 
+/* CPU-driven batched form of the same update (Algorithm 1; Section 2.5),
+ * for comparison with the fused kernel: each Newton iteration is an assemble
+ * launch over all points, one batched LU solve of all Jacobians
+ * (lupp_batched_solve, interleaved layout) and an update launch, after which
+ * the host reads one counter of points still iterating. Finished points are
+ * carried through the remaining batched solves but do not change, so every
+ * output (sig, state, iters, status, tangent) is bitwise the one
+ * constitutive_update computes. Blocks the calling thread until done (it
+ * synchronises `stream` once per iteration). The context keeps the device
+ * workspace (about 8 (kind^2 + 2 kind + 4) bytes per point) between calls.
+ *   flags      : 0, or LUPP_BATCHED_GRAPH to capture one iteration in a HIP
+ *                graph and replay it (one launch per iteration).
+ *   iterations : NULL, or receives the number of host-driven iterations.
+ * Returns as constitutive_update, -6 for unknown flags, LUPP_E_UNSUPPORTED if
+ * (kind^2 + 1) * count * 8 bytes reach 2^31. */
+#define LUPP_BATCHED_GRAPH 1u
+int constitutive_update_batched(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law,
+                                double tol, int maxit, unsigned flags, void *stream,
+                                int *iterations);
+
 /* ---------------------------------------------------------------------------
  * Time-step sweeps captured in a HIP graph. An implicit constitutive update
  * runs at every step of the global solution (Section 2.5); a sweep records

@@ -24,6 +24,7 @@ struct lupp_ctx {
     int forced_wpb = 0;
     lupp::Choice table[33][2][2]; /* [n][layout][batch bucket] */
     lupp::RaggedWs *ragged_ws = nullptr; /* device workspace of the ragged path */
+    lupp::BnWs *bn_ws = nullptr;         /* device workspace of the batched Newton */
 };
 
 namespace lupp {
@@ -91,11 +92,12 @@ int lupp_create(lupp_ctx **ctx, int device)
 void lupp_destroy(lupp_ctx *ctx)
 {
     if (ctx == nullptr) return;
-    if (ctx->ragged_ws != nullptr) {
+    if (ctx->ragged_ws != nullptr || ctx->bn_ws != nullptr) {
         int cur = 0;
         hipGetDevice(&cur);
         hipSetDevice(ctx->device);
         ragged_ws_destroy(ctx->ragged_ws);
+        bn_ws_destroy(ctx->bn_ws);
         hipSetDevice(cur);
     }
     delete ctx;
@@ -350,6 +352,36 @@ int constitutive_update(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *l
     hipGetDevice(&cur);
     if (cur != ctx->device) hipSetDevice(ctx->device);
     const int rc = constitutive_launch(pts, law, tol, maxit, (hipStream_t)stream);
+    if (cur != ctx->device) hipSetDevice(cur);
+    return rc;
+}
+
+int constitutive_update_batched(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law,
+                                double tol, int maxit, unsigned flags, void *stream,
+                                int *iterations)
+{
+    if (iterations) *iterations = 0;
+    if (ctx == nullptr) return -1;
+    if (pts == nullptr || pts->count < 0 || pts->ld < pts->count) return -2;
+    if (law == nullptr || (law->kind != LUPP_LAW_NORTON7 && law->kind != LUPP_LAW_NORTON_AF13))
+        return -3;
+    if (!(tol >= 0.0)) return -4;
+    if (maxit < 0 || maxit > LUPP_MAXIT_LIMIT) return -5;
+    if ((flags & ~LUPP_BATCHED_GRAPH) != 0) return -6;
+    if (pts->count == 0) return 0;
+    if (pts->deps == nullptr || pts->state == nullptr || pts->sig == nullptr ||
+        pts->iters == nullptr || pts->status == nullptr)
+        return -2;
+    /* the batched SoA solve addresses the largest Jacobian row with 32 bits */
+    if (((int64_t)law->kind * law->kind + 1) * pts->count * 8 >= ((int64_t)1 << 31))
+        return LUPP_E_UNSUPPORTED;
+    int cur = 0;
+    hipGetDevice(&cur);
+    if (cur != ctx->device) hipSetDevice(ctx->device);
+    if (ctx->bn_ws == nullptr) ctx->bn_ws = bn_ws_create();
+    const int rc = constitutive_batched_run(ctx, ctx->bn_ws, pts, law, tol, maxit,
+                                            (flags & LUPP_BATCHED_GRAPH) != 0,
+                                            (hipStream_t)stream, iterations);
     if (cur != ctx->device) hipSetDevice(cur);
     return rc;
 }

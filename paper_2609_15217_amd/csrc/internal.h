@@ -40,6 +40,14 @@ constexpr int64_t kSmallBatch = 32768;
 bool tuned_choice(int n, int layout, int bucket, int *variant, int *lanes, int *wpb);
 constexpr int kThreadMaxN = 13;
 
+/* CPU-driven batched Newton (batched_newton.hip): workspace owned by a
+ * context, and the host-driven iteration loop. */
+struct BnWs;
+BnWs *bn_ws_create();
+void bn_ws_destroy(BnWs *ws);
+int constitutive_batched_run(lupp_ctx *ctx, BnWs *ws, const lupp_points *pts, const lupp_law *law,
+                             double tol, int maxit, bool graph, hipStream_t st, int *iterations);
+
 /* Constitutive update launcher (constitutive.hip). */
 int constitutive_launch(const lupp_points *pts, const lupp_law *law, double tol, int maxit,
                         hipStream_t stream);

@@ -130,7 +130,7 @@ EXPORTED = ["lupp_create", "lupp_destroy", "lupp_batched_solve", "lupp_batched_s
             "lupp_server_add_points", "lupp_server_read_points", "lupp_server_submit",
             "lupp_server_poll", "lupp_server_wait", "lupp_server_get_stats",
             "lupp_server_reset_stats", "lupp_sweep_create", "lupp_sweep_launch",
-            "lupp_sweep_destroy"]
+            "lupp_sweep_destroy", "constitutive_update_batched"]
 
 
 class LuppError(RuntimeError):
@@ -256,6 +256,22 @@ def constitutive_update(ctx: Context, pts: lupp_points, law: lupp_law, tol: floa
                         stream=None) -> int:
     return _constitutive_update(ctx.handle, ctypes.byref(pts), ctypes.byref(law), tol, maxit,
                                 _stream(stream))
+
+
+LUPP_BATCHED_GRAPH = 1
+_constitutive_update_batched = _sig("constitutive_update_batched", ctypes.c_int,
+                                    [_P, ctypes.POINTER(lupp_points), ctypes.POINTER(lupp_law),
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_uint, _P,
+                                     ctypes.POINTER(ctypes.c_int)])
+
+
+def constitutive_update_batched(ctx: Context, pts: lupp_points, law: lupp_law, tol: float,
+                                maxit: int, flags: int = 0, stream=None):
+    """Returns (rc, host-driven iterations)."""
+    k = ctypes.c_int(0)
+    rc = _constitutive_update_batched(ctx.handle, ctypes.byref(pts), ctypes.byref(law), tol, maxit,
+                                      flags, _stream(stream), ctypes.byref(k))
+    return rc, k.value
 
 
 # --------------------------------------------------------------------------

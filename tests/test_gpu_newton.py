@@ -190,3 +190,69 @@ def test_tangent_elastic_limit(L, ctx):
     D = lam * np.outer(one, one) + 2 * mu * np.eye(6)
     assert np.all(g["status"] == 0)
     assert np.abs(g["tangent"] - D).max() <= 1e-12 * np.abs(D).max()
+
+
+def run_update(L, ctx, law: Law, deps, batched_flags=None, maxit=20, tangent=False, state=None):
+    """Fused (batched_flags None) or CPU-driven batched update on fresh buffers."""
+    count = deps.shape[0]
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(deps.T.copy()).to(dev)
+    st = torch.zeros((law.kind, count), dtype=torch.float64, device=dev)
+    if state is not None:
+        st.copy_(torch.from_numpy(state.T.copy()))
+    sig = torch.full((6, count), np.nan, dtype=torch.float64, device=dev)
+    it = torch.full((count,), -1, dtype=torch.int32, device=dev)
+    ss = torch.full((count,), -1, dtype=torch.int32, device=dev)
+    tan = torch.full((36, count), np.nan, dtype=torch.float64, device=dev) if tangent else None
+    pts = L.points(d, st, sig, it, ss, tan)
+    lw = L.make_law(law.kind, law.E, law.nu, law.A, law.m, law.C, law.D, law.dt)
+    k = None
+    if batched_flags is None:
+        assert L.constitutive_update(ctx, pts, lw, 1e-12, maxit) == 0
+    else:
+        rc, k = L.constitutive_update_batched(ctx, pts, lw, 1e-12, maxit, batched_flags)
+        assert rc == 0, L.lupp_error_string(rc)
+    torch.cuda.synchronize()
+    out = [t.cpu().numpy() for t in (st, sig, it, ss) + ((tan,) if tangent else ())]
+    return out, k
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("kind", [7, 13])
+def test_batched_newton_is_bitwise_the_fused_update(L, ctx, kind, flags):
+    """Algorithm 1 (host-driven iterations, batched LU) against Algorithm 2
+    (fused kernel): identical outputs, eager and graph-captured iterations."""
+    law = Law(kind=kind)
+    deps = newton_points(20000, seed=70 + kind)
+    ref, _ = run_update(L, ctx, law, deps, tangent=True)
+    got, k = run_update(L, ctx, law, deps, batched_flags=flags, tangent=True)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b, equal_nan=True)
+    iters, status = ref[2], ref[3]
+    assert k == iters.max() + 1 + int((status == 2).any())
+
+
+def test_batched_newton_edge_cases(L, ctx):
+    law = Law(kind=13)
+    # maxit = 0, a non-finite increment, zero loading and a second call on the
+    # same (cached) workspace with fewer points
+    deps = newton_points(3000, seed=75)
+    deps[5, 2] = np.nan
+    deps[7] = 0.0
+    for maxit in (0, 3, 20):
+        ref, _ = run_update(L, ctx, law, deps, maxit=maxit)
+        got, k = run_update(L, ctx, law, deps, batched_flags=1, maxit=maxit)
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b, equal_nan=True)
+        assert k <= maxit + 2
+    small = deps[:100]
+    ref, _ = run_update(L, ctx, law, small, state=np.full((100, 13), 1e-4))
+    got, _ = run_update(L, ctx, law, small, batched_flags=0, state=np.full((100, 13), 1e-4))
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b, equal_nan=True)
+    e = torch.empty(0, dtype=torch.float64, device="cuda:0")
+    ei = torch.empty(0, dtype=torch.int32, device="cuda:0")
+    pts = L.lupp_points(0, 0, 0, 0, 0, 0, 0, None)
+    assert L.constitutive_update_batched(ctx, pts, L.make_law(7), 1e-12, 20)[0] == 0
+    assert L.constitutive_update_batched(ctx, pts, L.make_law(7), 1e-12, 20, flags=4)[0] == -6
+    del e, ei
