@@ -454,6 +454,24 @@ def main():
             ms = float(np.mean(times))
             its = it.double().sum().item()
             conv = int((stt == 0).sum().item())
+            # every mapping of the fused update (one lane or T lanes per point)
+            mapping = {}
+            _, default_lanes = L.lupp_get_newton_variant(ctx, kind)
+            for lanes in ((1, 4, 8) if kind == 7 else (1, 8, 16)):
+                assert L.lupp_set_newton_variant(ctx, kind, lanes) == 0
+                mt = []
+                for r in range(args.warmup + min(args.steps, 3)):
+                    st.zero_()
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    assert L.constitutive_update(ctx, pts, law, 1e-12, 20, stream) == 0
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    if r >= args.warmup:
+                        mt.append(e0.elapsed_time(e1))
+                mapping[f"lanes{lanes}_ms"] = round(float(np.mean(mt)), 3)
+            assert L.lupp_set_newton_variant(ctx, kind, 0) == 0
             # the same update plus the consistent tangent of every converged
             # point (one multi-right-hand-side solve after convergence)
             tan = torch.empty((36, count), dtype=torch.float64, device=dev)
@@ -491,6 +509,8 @@ def main():
                                        "newton_iterations_per_s": round(its / (ms * 1e-3)),
                                        "mean_solves_per_point": round(its / count, 3),
                                        "converged": conv,
+                                       "default_lanes_per_point": default_lanes,
+                                       "mapping": mapping,
                                        "with_tangent_ms": round(tms, 3),
                                        "with_tangent_updates_per_s": round(count / (tms * 1e-3)),
                                        "batched_cpu_driven_ms": round(bt["batched"][0], 3),

@@ -214,6 +214,16 @@ typedef struct {
 int constitutive_update(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law, double tol,
                         int maxit, void *stream);
 
+/* Mapping of the fused update for law `kind` on this context (Section 3.2:
+ * single- versus multi-threaded device-callable solvers): lanes = 1 runs one
+ * lane per point (the whole Jacobian in one lane's registers); 4 or 8 (kind
+ * 7) and 8 or 16 (kind 13) run that many lanes per point, each building its
+ * own Jacobian rows, with the lanes LU. Results are bitwise the same for
+ * every mapping. 0 restores the measured default. Calls that request the
+ * tangent always run one lane per point. Returns -k for the k-th argument. */
+int lupp_set_newton_variant(lupp_ctx *ctx, int kind, int lanes);
+int lupp_get_newton_variant(const lupp_ctx *ctx, int kind, int *lanes);
+
 /* CPU-driven batched form of the same update (Algorithm 1; Section 2.5),
  * for comparison with the fused kernel: each Newton iteration is an assemble
  * launch over all points, one batched LU solve of all Jacobians

@@ -363,11 +363,15 @@ __device__ __forceinline__ int lanes_pivot_owner(const double (&a)[(N + T - 1) /
 }
 
 /* Back substitution, column j descending: x_j lives in the row at position j;
- * its owner divides, broadcasts x_j, and the rows above eliminate it. */
-template <int N, int T>
+ * its owner divides, broadcasts x_j, and the rows above eliminate it. Every
+ * lane of the segment sees every x_j: x_sink(j, x_j) is called by all lanes
+ * (a solver whose callers need the whole solution in every lane gets it
+ * without further communication). */
+template <int N, int T, typename XSink>
 __device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) / T][N],
                                                  double (&b)[(N + T - 1) / T],
-                                                 const int (&pos)[(N + T - 1) / T], int seg_base)
+                                                 const int (&pos)[(N + T - 1) / T], int seg_base,
+                                                 XSink x_sink)
 {
     constexpr int K = lanes_shape<N, T>::K;
     const unsigned lowmask = T >= 32 ? 0xffffffffu : ((1u << (T & 31)) - 1u);
@@ -386,6 +390,7 @@ __device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) /
         const unsigned ob = (unsigned)(__ballot(mine) >> (unsigned)seg_base) & lowmask;
         const int owner = seg_base + (int)__builtin_ctz(ob | (1u << 31));
         const double x = bcast_f64(xl, owner);
+        x_sink(j, x);
         static_for<0, K>(LUPP_SF(sc) {
             constexpr int s = decltype(sc)::value;
             if (pos[s] == j) b[s] = x;
@@ -405,11 +410,11 @@ __device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) /
  * The pivot row reaches the other lanes of the segment by ds_bpermute, and
  * the trailing update runs under the exec mask of the trailing rows
  * (pos > k). No LDS allocation is needed. */
-template <int N, int T, typename IpivSink>
+template <int N, int T, typename IpivSink, typename XSink>
 __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N],
                                                  double (&b)[(N + T - 1) / T],
                                                  int (&pos)[(N + T - 1) / T], int seg_base,
-                                                 IpivSink ipiv_k)
+                                                 IpivSink ipiv_k, XSink x_sink)
 {
     constexpr int K = lanes_shape<N, T>::K;
     constexpr int CH = 8; /* pivot-row columns broadcast per chunk */
@@ -487,8 +492,17 @@ __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N]
             }
         }
     });
-    if (info == 0) lanes_back_subst<N, T>(a, b, pos, seg_base);
+    if (info == 0) lanes_back_subst<N, T>(a, b, pos, seg_base, x_sink);
     return info;
+}
+
+template <int N, int T, typename IpivSink>
+__device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N],
+                                                 double (&b)[(N + T - 1) / T],
+                                                 int (&pos)[(N + T - 1) / T], int seg_base,
+                                                 IpivSink ipiv_k)
+{
+    return lanes_getrf_solve<N, T>(a, b, pos, seg_base, ipiv_k, [](int, double) {});
 }
 
 }  // namespace lupp

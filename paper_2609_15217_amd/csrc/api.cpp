@@ -25,6 +25,8 @@ struct lupp_ctx {
     lupp::Choice table[33][2][2]; /* [n][layout][batch bucket] */
     lupp::RaggedWs *ragged_ws = nullptr; /* device workspace of the ragged path */
     lupp::BnWs *bn_ws = nullptr;         /* device workspace of the batched Newton */
+    int newton_lanes[2] = {lupp::newton_default_lanes(LUPP_LAW_NORTON7),
+                           lupp::newton_default_lanes(LUPP_LAW_NORTON_AF13)};
 };
 
 namespace lupp {
@@ -351,9 +353,29 @@ int constitutive_update(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *l
     int cur = 0;
     hipGetDevice(&cur);
     if (cur != ctx->device) hipSetDevice(ctx->device);
-    const int rc = constitutive_launch(pts, law, tol, maxit, (hipStream_t)stream);
+    const int lanes = ctx->newton_lanes[law->kind == LUPP_LAW_NORTON7 ? 0 : 1];
+    const int rc = constitutive_launch(pts, law, tol, maxit, lanes, (hipStream_t)stream);
     if (cur != ctx->device) hipSetDevice(cur);
     return rc;
+}
+
+int lupp_set_newton_variant(lupp_ctx *ctx, int kind, int lanes)
+{
+    if (ctx == nullptr) return -1;
+    if (kind != LUPP_LAW_NORTON7 && kind != LUPP_LAW_NORTON_AF13) return -2;
+    if (lanes == 0) lanes = newton_default_lanes(kind);
+    if (!newton_lanes_supported(kind, lanes)) return -3;
+    ctx->newton_lanes[kind == LUPP_LAW_NORTON7 ? 0 : 1] = lanes;
+    return 0;
+}
+
+int lupp_get_newton_variant(const lupp_ctx *ctx, int kind, int *lanes)
+{
+    if (ctx == nullptr) return -1;
+    if (kind != LUPP_LAW_NORTON7 && kind != LUPP_LAW_NORTON_AF13) return -2;
+    if (lanes == nullptr) return -3;
+    *lanes = ctx->newton_lanes[kind == LUPP_LAW_NORTON7 ? 0 : 1];
+    return 0;
 }
 
 int constitutive_update_batched(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law,

@@ -69,13 +69,134 @@ __global__ void __launch_bounds__(256) k_newton(lupp_points pts, LawK P, double 
     }
 }
 
+/* Lanes-per-point form of the same fused update (Section 3.2.1 and Section
+ * 3.3: a multi-threaded device-callable solver embedded in the law, with the
+ * law's work partitioned across the cooperating threads). T lanes of a wave
+ * share one point: every lane evaluates the law's common part and the whole
+ * residual redundantly (so the stop rules need no communication), builds
+ * only the Jacobian rows it owns (rows t, t + T, ...), and the segment solves
+ * with the lanes LU, whose back substitution hands every x_j to every lane.
+ * The Jacobian entries, the pivots and the operation order are those of the
+ * one-lane-per-point kernel, so the results are bitwise the same; the
+ * per-lane register footprint is a fraction of the 13 x 13 matrix.
+ * The tangent is left to the one-lane-per-point kernel. */
+template <int NU, int T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    k_newton_lanes(lupp_points pts, LawK P, double tol, int maxit)
+{
+    constexpr int K = (NU + T - 1) / T, SPW = 64 / T;
+    const int lane = (int)__lane_id();
+    const int g = lane / T, t = lane % T;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t p0 = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave) * SPW;
+    const int64_t rem = pts.count - p0;
+    const uint32_t nvalid = (uint32_t)(rem <= 0 ? 0 : (rem < SPW ? rem : SPW));
+    const uint32_t nb = nvalid * 8u;
+    const uint32_t vo = (uint32_t)g < nvalid ? (uint32_t)g * 8u : kOutOfRange;
+
+    double de[6], st[NU], y[NU];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) de[c] = buf_load_f64(make_rsrc(pts.deps + c * pts.ld + p0, nb), vo, 0);
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+        st[c] = buf_load_f64(make_rsrc(pts.state + c * pts.ld + p0, nb), vo, 0);
+        y[c] = 0.0;
+    }
+
+    LawC<NU> C;
+    int status = 1, it = 0;
+    for (;; ++it) {
+        law_common<NU>(P, de, st, y, C);
+        bool finite = true;
+        double nrm = 0.0;
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+            finite = finite && __builtin_isfinite(C.F[i]);
+            nrm = fmax(nrm, fabs(C.F[i]));
+        }
+        if (!finite) { status = 3; break; }
+        if (nrm < tol) { status = 0; break; }
+        if (it == maxit) { status = 1; break; }
+        double a[K][NU], b[K];
+        int pos[K];
+        static_for<0, K>(LUPP_SF(sc) {
+            constexpr int s = decltype(sc)::value;
+            const int r = t + s * T;
+            pos[s] = r < NU ? r : -1;
+            if (r < NU) {
+                law_jac_row<NU>(P, C, r, a[s]);
+                b[s] = -select_at<NU>(C.F, r);
+            } else {
+#pragma unroll
+                for (int c = 0; c < NU; ++c) a[s][c] = 0.0;
+                b[s] = 0.0;
+            }
+        });
+        /* x += dx as the back substitution hands out each dx_j (a zero pivot
+         * skips the substitution, so y is then unchanged) */
+        const int inf = lanes_getrf_solve<NU, T>(a, b, pos, g * T, [](int, int) {},
+                                                 [&](int j, double x) { y[j] = y[j] + x; });
+        if (inf != 0) { status = 2; break; }
+    }
+
+    /* lane 0 of each segment writes the point's results */
+    const uint32_t vw = t == 0 ? vo : kOutOfRange;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) buf_store_f64(make_rsrc(pts.sig + c * pts.ld + p0, nb), vw, 0, C.sig[c]);
+    const uint32_t vs = status == 0 ? vw : kOutOfRange;
+#pragma unroll
+    for (int c = 0; c < NU; ++c)
+        buf_store_f64(make_rsrc(pts.state + c * pts.ld + p0, nb), vs, 0, st[c] + y[c]);
+    const uint32_t vi = t == 0 && (uint32_t)g < nvalid ? (uint32_t)g * 4u : kOutOfRange;
+    buf_store_i32(make_rsrc(pts.iters + p0, nvalid * 4u), vi, 0, it);
+    buf_store_i32(make_rsrc(pts.status + p0, nvalid * 4u), vi, 0, status);
+}
+
+template <int NU, int T>
+static void launch_newton_lanes(const lupp_points *pts, const LawK &P, double tol, int maxit,
+                                hipStream_t stream)
+{
+    constexpr int per_block = 4 * (64 / T); /* 4 waves */
+    const int64_t blocks = (pts->count + per_block - 1) / per_block;
+    hipLaunchKernelGGL((k_newton_lanes<NU, T>), dim3((unsigned)blocks), dim3(256), 0, stream, *pts, P,
+                       tol, maxit);
+}
+
+/* Default mapping per law, measured on gfx950 (2^20 points of the benchmark
+ * increments, mean 17.7 solves per point): one lane per point wins for both
+ * laws - 7 unknowns: 1.33 ms against 4.5 ms (4 lanes) and 6.6 ms (8 lanes);
+ * 13 unknowns: 7.6 ms, despite 512 VGPRs with some scratch and one wave per
+ * SIMD, against 17.9 ms (8 lanes) and 23 ms (16 lanes, 247 VGPRs, two
+ * waves). Every lane of a group repeats the law's common part (pow, sqrt,
+ * divisions), and the lanes LU's pivot search and broadcasts cost more than
+ * the occupancy they buy back. */
+int newton_default_lanes(int) { return 1; }
+
+bool newton_lanes_supported(int kind, int lanes)
+{
+    if (lanes == 1) return true;
+    if (kind == LUPP_LAW_NORTON7) return lanes == 4 || lanes == 8;
+    if (kind == LUPP_LAW_NORTON_AF13) return lanes == 8 || lanes == 16;
+    return false;
+}
+
 int constitutive_launch(const lupp_points *pts, const lupp_law *law, double tol, int maxit,
-                        hipStream_t stream)
+                        int lanes, hipStream_t stream)
 {
     const LawK P = law_constants(law);
+    const bool tan = pts->tangent != nullptr;
+    if (!tan && lanes > 1) {
+        if (law->kind == LUPP_LAW_NORTON7) {
+            if (lanes == 4) launch_newton_lanes<7, 4>(pts, P, tol, maxit, stream);
+            else launch_newton_lanes<7, 8>(pts, P, tol, maxit, stream);
+        } else {
+            if (lanes == 8) launch_newton_lanes<13, 8>(pts, P, tol, maxit, stream);
+            else launch_newton_lanes<13, 16>(pts, P, tol, maxit, stream);
+        }
+        return hip_err(hipGetLastError());
+    }
     const int threads = 256;
     const int64_t blocks = (pts->count + threads - 1) / threads;
-    const bool tan = pts->tangent != nullptr;
     const dim3 g((unsigned)blocks), b(threads);
     if (law->kind == LUPP_LAW_NORTON7) {
         if (tan) hipLaunchKernelGGL((k_newton<7, true>), g, b, 0, stream, *pts, P, tol, maxit);

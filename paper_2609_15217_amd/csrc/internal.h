@@ -49,8 +49,13 @@ int constitutive_batched_run(lupp_ctx *ctx, BnWs *ws, const lupp_points *pts, co
                              double tol, int maxit, bool graph, hipStream_t st, int *iterations);
 
 /* Constitutive update launcher (constitutive.hip). */
+/* lanes: 1 = one lane per point, else lanes per point (see
+ * newton_lanes_supported); tangent requests always use one lane per point. */
 int constitutive_launch(const lupp_points *pts, const lupp_law *law, double tol, int maxit,
-                        hipStream_t stream);
+                        int lanes, hipStream_t stream);
+bool newton_lanes_supported(int kind, int lanes);
+/* Measured default mapping of the fused update per law kind (gfx950). */
+int newton_default_lanes(int kind);
 const void *constitutive_kernel_symbol(int kind, bool tangent);
 
 /* Ragged batch (ragged.hip): device workspace owned by a context. */

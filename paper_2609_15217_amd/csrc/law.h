@@ -23,29 +23,36 @@ struct LawK {
     double lam, two_mu, dtA, m, c23, D;
 };
 
-/* Residual, Jacobian (J[c][r] = dF_r/dy_c, the solver's column-major form)
- * and stress at the unknowns y. */
+/* What the residual and every Jacobian row need at the unknowns y: stress,
+ * flow direction N, back-strain alpha, the scalars of the Jacobian blocks,
+ * and the residual F itself. */
 template <int NU>
-__device__ __forceinline__ void law_assemble(const LawK &P, const double (&de)[6],
-                                             const double (&st)[NU], const double (&y)[NU],
-                                             double (&F)[NU], double (&J)[NU][NU], double (&sig)[6])
+struct LawC {
+    double sig[6], Nv[6], al[6], F[NU];
+    double inv, dp, gd, dp2mu, cdp, nmean;
+};
+
+template <int NU>
+__device__ __forceinline__ void law_common(const LawK &P, const double (&de)[6],
+                                           const double (&st)[NU], const double (&y)[NU],
+                                           LawC<NU> &C)
 {
     constexpr bool af = (NU == 13);
-    double e[6], xi[6], al[6], Nv[6];
+    double e[6], xi[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) e[i] = st[i] + y[i];
     const double tr = e[0] + e[1] + e[2];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) sig[i] = P.two_mu * e[i] + (i < 3 ? P.lam * tr : 0.0);
-    const double mean = (sig[0] + sig[1] + sig[2]) / 3.0;
+    for (int i = 0; i < 6; ++i) C.sig[i] = P.two_mu * e[i] + (i < 3 ? P.lam * tr : 0.0);
+    const double mean = (C.sig[0] + C.sig[1] + C.sig[2]) / 3.0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        xi[i] = sig[i] - (i < 3 ? mean : 0.0);
+        xi[i] = C.sig[i] - (i < 3 ? mean : 0.0);
         if constexpr (af) {
-            al[i] = st[7 + i] + y[7 + i];
-            xi[i] = xi[i] - P.c23 * al[i];
+            C.al[i] = st[7 + i] + y[7 + i];
+            xi[i] = xi[i] - P.c23 * C.al[i];
         } else {
-            al[i] = 0.0;
+            C.al[i] = 0.0;
         }
     }
     double q = 0.0;
@@ -53,58 +60,139 @@ __device__ __forceinline__ void law_assemble(const LawK &P, const double (&de)[6
     for (int i = 0; i < 6; ++i) q += xi[i] * xi[i];
     const double seq = sqrt(1.5 * q);
     const bool pl = seq > 0.0;
-    const double inv = pl ? 1.0 / seq : 0.0;
+    C.inv = pl ? 1.0 / seq : 0.0;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) Nv[i] = pl ? 1.5 * xi[i] / seq : 0.0;
+    for (int i = 0; i < 6; ++i) C.Nv[i] = pl ? 1.5 * xi[i] / seq : 0.0;
 
     const double dp = y[6];
     const double sm1 = pl ? pow(seq, P.m - 1.0) : 0.0;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) F[i] = y[i] + dp * Nv[i] - de[i];
-    F[6] = dp - P.dtA * (pl ? pow(seq, P.m) : 0.0);
+    for (int i = 0; i < 6; ++i) C.F[i] = y[i] + dp * C.Nv[i] - de[i];
+    C.F[6] = dp - P.dtA * (pl ? pow(seq, P.m) : 0.0);
     if constexpr (af) {
 #pragma unroll
-        for (int i = 0; i < 6; ++i) F[7 + i] = y[7 + i] - dp * Nv[i] + P.D * dp * al[i];
+        for (int i = 0; i < 6; ++i) C.F[7 + i] = y[7 + i] - dp * C.Nv[i] + P.D * dp * C.al[i];
     }
+    C.dp = dp;
+    C.nmean = (C.Nv[0] + C.Nv[1] + C.Nv[2]) / 3.0;
+    C.gd = P.dtA * P.m * sm1; /* d(dt A seq^m)/dseq */
+    C.dp2mu = dp * P.two_mu;
+    C.cdp = P.c23 * dp;
+}
 
-    /* G = dN/dxi = (3/2 I - N N^T) / seq;  GK = G K (K: deviatoric projector)
-     * so that dN/d(d_eel) = 2 mu GK and dN/d(d_alpha) = -2/3 C G. */
-    double G[6][6], GK[6][6];
+/* The Jacobian blocks. G = dN/dxi = (3/2 I - N N^T) / seq and GK = G K (K:
+ * the deviatoric projector), so that dN/d(d_eel) = 2 mu GK and
+ * dN/d(d_alpha) = -2/3 C G. Row a of G and GK needs only N_a: */
+__device__ __forceinline__ void law_g_row(const double (&Nv)[6], double inv, int a, double Na,
+                                          double (&G)[6], double (&GK)[6])
+{
 #pragma unroll
-    for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b) G[b] = ((a == b ? 1.5 : 0.0) - Na * Nv[b]) * inv;
+    const double rowmean = (G[0] + G[1] + G[2]) / 3.0;
 #pragma unroll
-        for (int b = 0; b < 6; ++b) G[a][b] = ((a == b ? 1.5 : 0.0) - Nv[a] * Nv[b]) * inv;
+    for (int b = 0; b < 6; ++b) GK[b] = G[b] - (b < 3 ? rowmean : 0.0);
+}
+
+/* v[i] for a lane-varying i by a compare/select chain. Each element passes
+ * through an empty asm so that the compiler cannot turn the chain back into
+ * a dynamically indexed (scratch-memory) array load. */
+template <int M>
+__device__ __forceinline__ double select_at(const double (&v)[M], int i)
+{
+    double r = v[0];
+#pragma unroll
+    for (int k = 1; k < M; ++k) {
+        double x = v[k];
+        asm volatile("" : "+v"(x));
+        r = (i == k) ? x : r;
+    }
+    return r;
+}
+
+/* Row r (0 <= r < NU) of the Jacobian, row[c] = dF_r/dy_c; r may differ
+ * between lanes. Every entry is the expression law_jacobian uses. */
+template <int NU>
+__device__ __forceinline__ void law_jac_row(const LawK &P, const LawC<NU> &C, int r,
+                                            double (&row)[NU])
+{
+    constexpr bool af = (NU == 13);
+    /* N_a and alpha_a of the row's component, by selects (no dynamic index) */
+    const int a = r < 6 ? r : r - 7;
+    const double Na = select_at<6>(C.Nv, a);
+    const double ala = af ? select_at<6>(C.al, a) : 0.0;
+    if (r == 6) {
+#pragma unroll
+        for (int b = 0; b < 6; ++b) row[b] = -C.gd * P.two_mu * (C.Nv[b] - (b < 3 ? C.nmean : 0.0));
+        row[6] = 1.0;
+        if constexpr (af) {
+#pragma unroll
+            for (int b = 0; b < 6; ++b) row[7 + b] = P.c23 * C.gd * C.Nv[b];
+        }
+        return;
+    }
+    double G[6], GK[6];
+    law_g_row(C.Nv, C.inv, a, Na, G, GK);
+    if (r < 6) {
+#pragma unroll
+        for (int b = 0; b < 6; ++b) row[b] = (a == b ? 1.0 : 0.0) + C.dp2mu * GK[b];
+        row[6] = Na;
+        if constexpr (af) {
+#pragma unroll
+            for (int b = 0; b < 6; ++b) row[7 + b] = -C.cdp * G[b];
+        }
+    } else if constexpr (af) {
+#pragma unroll
+        for (int b = 0; b < 6; ++b) row[b] = -C.dp2mu * GK[b];
+        row[6] = -Na + P.D * ala;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) row[7 + b] = (a == b ? 1.0 + P.D * C.dp : 0.0) + C.cdp * G[b];
+    }
+}
+
+/* The whole Jacobian, J[c][r] = dF_r/dy_c (the solver's column-major form). */
+template <int NU>
+__device__ __forceinline__ void law_jacobian(const LawK &P, const LawC<NU> &C, double (&J)[NU][NU])
+{
+    constexpr bool af = (NU == 13);
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
-        const double rowmean = (G[a][0] + G[a][1] + G[a][2]) / 3.0;
+        double G[6], GK[6];
+        law_g_row(C.Nv, C.inv, a, C.Nv[a], G, GK);
 #pragma unroll
-        for (int b = 0; b < 6; ++b) GK[a][b] = G[a][b] - (b < 3 ? rowmean : 0.0);
-    }
-    const double nmean = (Nv[0] + Nv[1] + Nv[2]) / 3.0;
-    const double gd = P.dtA * P.m * sm1; /* d(dt A seq^m)/dseq */
-    const double dp2mu = dp * P.two_mu;
+        for (int b = 0; b < 6; ++b) J[b][a] = (a == b ? 1.0 : 0.0) + C.dp2mu * GK[b];
+        J[6][a] = C.Nv[a];
+        if constexpr (af) {
 #pragma unroll
-    for (int b = 0; b < 6; ++b) {
-#pragma unroll
-        for (int a = 0; a < 6; ++a) J[b][a] = (a == b ? 1.0 : 0.0) + dp2mu * GK[a][b];
-        J[b][6] = -gd * P.two_mu * (Nv[b] - (b < 3 ? nmean : 0.0));
-        J[6][b] = Nv[b];
-    }
-    J[6][6] = 1.0;
-    if constexpr (af) {
-        const double cdp = P.c23 * dp;
-#pragma unroll
-        for (int b = 0; b < 6; ++b) {
-#pragma unroll
-            for (int a = 0; a < 6; ++a) {
-                J[7 + b][a] = -cdp * G[a][b];                 /* dF_e / d(d_alpha) */
-                J[b][7 + a] = -dp2mu * GK[a][b];              /* dF_a / d(d_eel)   */
-                J[7 + b][7 + a] = (a == b ? 1.0 + P.D * dp : 0.0) + cdp * G[a][b];
+            for (int b = 0; b < 6; ++b) {
+                J[7 + b][a] = -C.cdp * G[b];                  /* dF_e / d(d_alpha) */
+                J[b][7 + a] = -C.dp2mu * GK[b];               /* dF_a / d(d_eel)   */
+                J[7 + b][7 + a] = (a == b ? 1.0 + P.D * C.dp : 0.0) + C.cdp * G[b];
             }
-            J[7 + b][6] = P.c23 * gd * Nv[b];                 /* dF_p / d(d_alpha) */
-            J[6][7 + b] = -Nv[b] + P.D * al[b];               /* dF_a / d(dp)      */
+            J[6][7 + a] = -C.Nv[a] + P.D * C.al[a];           /* dF_a / d(dp)      */
         }
     }
+#pragma unroll
+    for (int b = 0; b < 6; ++b) J[b][6] = -C.gd * P.two_mu * (C.Nv[b] - (b < 3 ? C.nmean : 0.0));
+    J[6][6] = 1.0;
+    if constexpr (af) {
+#pragma unroll
+        for (int b = 0; b < 6; ++b) J[7 + b][6] = P.c23 * C.gd * C.Nv[b]; /* dF_p / d(d_alpha) */
+    }
+}
+
+/* Residual, Jacobian and stress at the unknowns y. */
+template <int NU>
+__device__ __forceinline__ void law_assemble(const LawK &P, const double (&de)[6],
+                                             const double (&st)[NU], const double (&y)[NU],
+                                             double (&F)[NU], double (&J)[NU][NU], double (&sig)[6])
+{
+    LawC<NU> C;
+    law_common<NU>(P, de, st, y, C);
+    law_jacobian<NU>(P, C, J);
+#pragma unroll
+    for (int i = 0; i < NU; ++i) F[i] = C.F[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) sig[i] = C.sig[i];
 }
 
 /* Consistent tangent (Section 2.5; Section 4.3: one multi-right-hand-side

@@ -54,7 +54,9 @@ int lupp_sweep_create(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law
         for (int t = 0; t < steps && rc == 0 && pts->count > 0; ++t) {
             lupp_points p = *pts;
             p.deps = pts->deps + (int64_t)t * deps_step;
-            rc = constitutive_launch(&p, law, tol, maxit, st);
+            int lanes = 1;
+            lupp_get_newton_variant(ctx, law->kind, &lanes);
+            rc = constitutive_launch(&p, law, tol, maxit, lanes, st);
         }
         /* always end the capture, also after a failed launch */
         const hipError_t e2 = hipStreamEndCapture(st, &sw->graph);

@@ -130,7 +130,8 @@ EXPORTED = ["lupp_create", "lupp_destroy", "lupp_batched_solve", "lupp_batched_s
             "lupp_server_add_points", "lupp_server_read_points", "lupp_server_submit",
             "lupp_server_poll", "lupp_server_wait", "lupp_server_get_stats",
             "lupp_server_reset_stats", "lupp_sweep_create", "lupp_sweep_launch",
-            "lupp_sweep_destroy", "constitutive_update_batched"]
+            "lupp_sweep_destroy", "constitutive_update_batched", "lupp_set_newton_variant",
+            "lupp_get_newton_variant"]
 
 
 class LuppError(RuntimeError):
@@ -256,6 +257,21 @@ def constitutive_update(ctx: Context, pts: lupp_points, law: lupp_law, tol: floa
                         stream=None) -> int:
     return _constitutive_update(ctx.handle, ctypes.byref(pts), ctypes.byref(law), tol, maxit,
                                 _stream(stream))
+
+
+_lupp_set_newton_variant = _sig("lupp_set_newton_variant", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int])
+_lupp_get_newton_variant = _sig("lupp_get_newton_variant", ctypes.c_int,
+                                [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)])
+
+
+def lupp_set_newton_variant(ctx: Context, kind: int, lanes: int) -> int:
+    return _lupp_set_newton_variant(ctx.handle, kind, lanes)
+
+
+def lupp_get_newton_variant(ctx: Context, kind: int):
+    v = ctypes.c_int(0)
+    rc = _lupp_get_newton_variant(ctx.handle, kind, ctypes.byref(v))
+    return rc, v.value
 
 
 LUPP_BATCHED_GRAPH = 1

@@ -256,3 +256,28 @@ def test_batched_newton_edge_cases(L, ctx):
     assert L.constitutive_update_batched(ctx, pts, L.make_law(7), 1e-12, 20)[0] == 0
     assert L.constitutive_update_batched(ctx, pts, L.make_law(7), 1e-12, 20, flags=4)[0] == -6
     del e, ei
+
+
+@pytest.mark.parametrize("kind,lanes", [(7, 4), (7, 8), (13, 8), (13, 16)])
+def test_lanes_per_point_newton_is_bitwise_the_lane_per_point_one(L, ctx, kind, lanes):
+    """T lanes per point (each building its Jacobian rows, lanes LU) against
+    one lane per point: identical outputs, including a non-finite increment,
+    zero loading, a loaded prior state and maxit = 0 / 3."""
+    law = Law(kind=kind)
+    deps = newton_points(6000, seed=85 + kind)
+    deps[11, 4] = np.inf
+    deps[13] = 0.0
+    state = None
+    for case in range(3):
+        for maxit in ((20,) if case < 2 else (0, 3)):
+            assert L.lupp_set_newton_variant(ctx, kind, 1) == 0
+            ref, _ = run_update(L, ctx, law, deps, maxit=maxit, state=state)
+            assert L.lupp_set_newton_variant(ctx, kind, lanes) == 0
+            assert L.lupp_get_newton_variant(ctx, kind) == (0, lanes)
+            got, _ = run_update(L, ctx, law, deps, maxit=maxit, state=state)
+            assert L.lupp_set_newton_variant(ctx, kind, 0) == 0
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b, equal_nan=True)
+        state = ref[0].T.copy()  # continue from the committed state
+    assert L.lupp_set_newton_variant(ctx, 7, 16) == -3
+    assert L.lupp_set_newton_variant(ctx, 9, 1) == -2
