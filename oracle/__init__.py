@@ -59,6 +59,9 @@ def lib():
         L.oracle_gesv_batch.argtypes = [ctypes.c_int, i64, P, ctypes.c_int, i64, P, i64, P, P, P,
                                         ctypes.c_int]
         L.oracle_gesv_batch.restype = None
+        L.oracle_gesv_batch_tiled.argtypes = [ctypes.c_int, i64, P, ctypes.c_int, i64, P, i64, P,
+                                              P, ctypes.c_int, ctypes.c_double, P, ctypes.c_int]
+        L.oracle_gesv_batch_tiled.restype = None
         L.oracle_gesv_ragged.argtypes = [i64, P, P, P, P, P, P, P, ctypes.c_int]
         L.oracle_gesv_ragged.restype = None
         L.oracle_law_eval.argtypes = [P, P, P, P, P, P, P]
@@ -120,6 +123,21 @@ def gesv_batch(A: np.ndarray, b: np.ndarray, threads: int | None = None, want_ga
     if want_gap:
         out["gap"] = gap
     return out
+
+
+def gesv_batch_tiled(A: np.ndarray, b: np.ndarray, tile: int, thresh: float = 1e-10,
+                     threads: int | None = None):
+    """Batched dgesv with tile-local pivoting (tile size `tile`, acceptance
+    threshold `thresh`). Returns dict(LU, x, ipiv, info, out_of_tile)."""
+    a = _f64(A).copy()
+    x = _f64(b).copy()
+    batch, n = a.shape[0], a.shape[1]
+    ipiv = np.zeros((batch, n), dtype=np.int32)
+    info = np.zeros(batch, dtype=np.int32)
+    oot = np.zeros(batch, dtype=np.int32)
+    lib().oracle_gesv_batch_tiled(n, batch, _p(a), n, n * n, _p(x), n, _p(ipiv), _p(info), tile,
+                                  thresh, _p(oot), threads or default_threads())
+    return {"LU": a, "x": x, "ipiv": ipiv, "info": info, "out_of_tile": oot}
 
 
 def gesv_ragged(n: np.ndarray, offA: np.ndarray, offB: np.ndarray, A: np.ndarray,

@@ -20,20 +20,46 @@
 /* stored below the diagonal, and the trailing submatrix (Schur complement)  */
 /* receives a_ij <- a_ij - l_ik * u_kj.                                      */
 /* ------------------------------------------------------------------------ */
-int oracle_getrf(int n, double *a, int lda, int32_t *ipiv, double *gap)
+/* Index of the first largest |col[i]| over lo <= i < hi (lowest row on ties). */
+static int oracle_argmax_abs(const double *col, int lo, int hi)
+{
+    int p = lo;
+    double best = fabs(col[lo]);
+    for (int i = lo + 1; i < hi; ++i) {
+        double v = fabs(col[i]);
+        if (v > best) {
+            best = v;
+            p = i;
+        }
+    }
+    return p;
+}
+
+/* ts <= 0 or ts >= n: textbook partial pivoting. Otherwise tile-local
+ * pivoting (Section 3.2.2, the Tiled solvers; Section 4.2): the candidates at
+ * step k are first the rows k .. (end of the diagonal tile of size ts holding
+ * k); only if the best of them is below thresh in magnitude does the search
+ * extend to every row k .. n-1 (counted in *oot). */
+static int oracle_getrf_rule(int n, double *a, int lda, int32_t *ipiv, double *gap, int ts,
+                             double thresh, int *oot)
 {
     int info = 0;
     double g = 1.0;
     for (int k = 0; k < n; ++k) {
-        int p = k;
-        double best = fabs(a[k + (int64_t)k * lda]);
-        for (int i = k + 1; i < n; ++i) {
-            double v = fabs(a[i + (int64_t)k * lda]);
-            if (v > best) {
-                best = v;
-                p = i;
+        const double *col = a + (int64_t)k * lda;
+        int p;
+        if (ts > 0 && ts < n) {
+            int k1 = (k / ts + 1) * ts;
+            if (k1 > n) k1 = n;
+            p = oracle_argmax_abs(col, k, k1);
+            if (fabs(col[p]) < thresh) {
+                p = oracle_argmax_abs(col, k, n);
+                if (oot != NULL) ++*oot;
             }
+        } else {
+            p = oracle_argmax_abs(col, k, n);
         }
+        const double best = fabs(col[p]);
         if (gap != NULL && k + 1 < n) {
             double second = -1.0;
             for (int i = k; i < n; ++i) {
@@ -65,6 +91,18 @@ int oracle_getrf(int n, double *a, int lda, int32_t *ipiv, double *gap)
     }
     if (gap != NULL) *gap = g;
     return info;
+}
+
+int oracle_getrf(int n, double *a, int lda, int32_t *ipiv, double *gap)
+{
+    return oracle_getrf_rule(n, a, lda, ipiv, gap, 0, 0.0, NULL);
+}
+
+int oracle_getrf_tiled(int n, double *a, int lda, int32_t *ipiv, int ts, double thresh,
+                       int *out_of_tile)
+{
+    if (out_of_tile != NULL) *out_of_tile = 0;
+    return oracle_getrf_rule(n, a, lda, ipiv, NULL, ts, thresh, out_of_tile);
 }
 
 /* Triangular solves (Section 2.2): apply the interchanges to b, then L y = P b
@@ -154,6 +192,36 @@ static void batch_body(void *p, int64_t lo, int64_t hi)
                                  c->ipiv + s * c->n, c->gap ? &g : NULL);
         if (c->gap) c->gap[s] = g;
     }
+}
+
+typedef struct {
+    int n, lda, ts;
+    double thresh;
+    int64_t strideA, strideB;
+    double *a, *b;
+    int32_t *ipiv, *info, *oot;
+} tiled_ctx;
+
+static void tiled_body(void *p, int64_t lo, int64_t hi)
+{
+    tiled_ctx *c = (tiled_ctx *)p;
+    for (int64_t s = lo; s < hi; ++s) {
+        int oot = 0;
+        double *a = c->a + s * c->strideA;
+        int32_t *ipiv = c->ipiv + s * c->n;
+        const int info = oracle_getrf_tiled(c->n, a, c->lda, ipiv, c->ts, c->thresh, &oot);
+        if (info == 0) oracle_getrs(c->n, a, c->lda, ipiv, c->b + s * c->strideB);
+        c->info[s] = info;
+        if (c->oot) c->oot[s] = oot;
+    }
+}
+
+void oracle_gesv_batch_tiled(int n, int64_t batch, double *a, int lda, int64_t strideA,
+                             double *b, int64_t strideB, int32_t *ipiv, int32_t *info, int ts,
+                             double thresh, int32_t *out_of_tile, int nthreads)
+{
+    tiled_ctx c = {n, lda, ts, thresh, strideA, strideB, a, b, ipiv, info, out_of_tile};
+    oracle_parallel_for(batch, nthreads, tiled_body, &c);
 }
 
 void oracle_gesv_batch(int n, int64_t batch, double *a, int lda, int64_t strideA,

@@ -45,6 +45,20 @@ void oracle_gesv_batch(int n, int64_t batch, double *a, int lda, int64_t strideA
                        double *b, int64_t strideB, int32_t *ipiv, int32_t *info,
                        double *gap, int nthreads);
 
+/* Tile-local partial pivoting, the pivoting rule of the paper's Tiled
+ * solvers (Section 3.2.2; Section 4.2): at step k the pivot is sought among
+ * rows k .. (last row of the diagonal tile of size ts that holds k) and, only
+ * if the best of them has magnitude below thresh, among all rows k .. n-1
+ * (an out-of-tile pivot, counted in *out_of_tile). Ties go to the lowest row;
+ * interchange, multipliers, update and solves are those of oracle_getrf /
+ * oracle_getrs. ts <= 0 or ts >= n is textbook partial pivoting. */
+int oracle_getrf_tiled(int n, double *a, int lda, int32_t *ipiv, int ts, double thresh,
+                       int *out_of_tile);
+/* Batched tiled dgesv (AoS, as oracle_gesv_batch); out_of_tile[batch] or NULL. */
+void oracle_gesv_batch_tiled(int n, int64_t batch, double *a, int lda, int64_t strideA,
+                             double *b, int64_t strideB, int32_t *ipiv, int32_t *info, int ts,
+                             double thresh, int32_t *out_of_tile, int nthreads);
+
 /* Ragged batch: system s has size n[s], matrix at a + offA[s] (lda = n[s]),
  * right-hand side and pivots at offset offB[s]. */
 void oracle_gesv_ragged(int64_t batch, const int32_t *n, const int64_t *offA,

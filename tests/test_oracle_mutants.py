@@ -33,6 +33,9 @@ MUTANTS = {
     "tangent_transposed": ("tan[6 * r + c] =", "tan[6 * c + r] ="),
     "tangent_drops_lambda": ("(r < 3 ? lam * tr : 0.0)", "0.0"),
     "tangent_wrong_rhs": ("x[i] = (i == c) ? 1.0 : 0.0;", "x[i] = (i == c + 1) ? 1.0 : 0.0;"),
+    "tiled_no_fallback": ("if (fabs(col[p]) < thresh) {", "if (0) {"),
+    "tiled_threshold_inverted": ("if (fabs(col[p]) < thresh) {", "if (fabs(col[p]) > thresh) {"),
+    "tiled_tile_end": ("int k1 = (k / ts + 1) * ts;", "int k1 = (k / ts + 1) * ts + 1;"),
 }
 
 
@@ -50,6 +53,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     env = dict(os.environ, ORACLE_SO=str(so))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_lupp.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_newton.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_newton.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_tiled.py")],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
