@@ -343,6 +343,31 @@ def main():
                 "traffic": load_traffic(dom_key), "kernel": dom_key,
                 "algorithmic_bytes_per_launch": bytes_per_system(dom["n"]) * BATCH}
 
+    # ------------------------------------------------------------- tile-local pivoting
+    # the same kernels under the Tiled solvers' pivoting rule (tile 4,
+    # threshold 1e-10): on these inputs no pivot leaves its tile
+    tiled = {}
+    if not args.only:
+        assert L.lupp_set_pivoting(ctx, 4, 1e-10) == 0
+        for k in keys:
+            if k[0] not in (8, 16, 32):
+                continue
+            tt = []
+            for r in range(args.warmup + min(args.steps, 3)):
+                restore()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                launch(k)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if r >= args.warmup:
+                    tt.append(e0.elapsed_time(e1))
+            base = next(r for r in per_kernel if (r["n"], r["layout"]) == k)["ms"]
+            tiled[f"n{k[0]}_{k[1]}"] = {"ms": round(float(np.mean(tt)), 4), "textbook_ms": base}
+        assert L.lupp_set_pivoting(ctx, 0, 0.0) == 0
+        log(f"tile-local pivoting: {tiled}")
+
     # ------------------------------------------------------------- ragged
     ragged = {}
     if not args.no_ragged:
@@ -599,6 +624,7 @@ def main():
         "roofline": roofline,
         "newton": newton,
         "sweep": sweep,
+        "tile_local_pivoting": tiled,
         "ragged": ragged,
         "serving": serving,
         "latency": lat,

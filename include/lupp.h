@@ -119,6 +119,20 @@ int lupp_batched_solve_ragged(lupp_ctx *ctx, int64_t batch, const int32_t *n,
                               const int64_t *offA, const int64_t *offB, double *A, double *b,
                               int32_t *ipiv, int32_t *info, unsigned flags, void *stream);
 
+/* Pivoting rule of later lupp_batched_solve calls on this context.
+ *   tile = 0 (the default): textbook partial pivoting (Section 2.2).
+ *   tile >= 1: tile-local pivoting, the rule of the paper's Tiled solvers
+ *   (Section 3.2.2; statistics in Section 4.2): at step k the pivot is sought
+ *   first among rows k .. (end of the diagonal tile of size `tile` holding
+ *   k), and among all rows k .. n-1 only when the best in-tile candidate has
+ *   magnitude below `threshold` (the paper uses 1e-10). It admits more pivot
+ *   growth than textbook pivoting. tile >= n is textbook pivoting.
+ * Applies to every variant of lupp_batched_solve (not to the ragged path or
+ * the Newton updates, which always pivot textbook-style). Returns -2 for
+ * tile outside 0..32, -3 for a negative or NaN threshold. */
+int lupp_set_pivoting(lupp_ctx *ctx, int tile, double threshold);
+int lupp_get_pivoting(const lupp_ctx *ctx, int *tile, double *threshold);
+
 /* Restrict later lupp_batched_solve calls on this context to one variant
  * (LUPP_VARIANT_AUTO restores the size-aware dispatch table). lanes is the
  * segment width for LUPP_VARIANT_LANES (2, 4, 8, 16 or 32), wpb the number of

@@ -74,25 +74,61 @@ __device__ __forceinline__ void static_for_down(F &&f)
 
 #define LUPP_SF(v) [&](auto v) __attribute__((always_inline))
 
+/* Last row + 1 of the pivot candidates tried first at step k: the end of the
+ * diagonal tile of size `tile` holding k (tile-local pivoting, the Tiled
+ * solvers' rule, Section 3.2.2), or n for textbook partial pivoting
+ * (tile <= 0). tile is uniform across the wave. */
+__device__ __forceinline__ int pivot_tile_end(int k, int n, int tile)
+{
+    if (tile <= 0) return n;
+    const int e = (k / tile + 1) * tile;
+    return e < n ? e : n;
+}
+
+/* Pivoting rule (all solvers): tile <= 0 is textbook partial pivoting (the
+ * default). tile >= 1 is tile-local pivoting: the candidates at step k are
+ * first the rows k .. pivot_tile_end - 1, and only if the best of them has
+ * magnitude below `thresh` are all rows k .. n-1 searched; ties go to the
+ * lowest row (position) either way. */
 template <int N, bool kFactors>
 __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)[N],
-                                                  int (&ipiv)[N])
+                                                  int (&ipiv)[N], int tile = 0,
+                                                  double thresh = 0.0)
 {
     int info = 0;
     static_for<0, N>(LUPP_SF(kc) {
         constexpr int k = decltype(kc)::value;
-        /* pivot search over rows k..N-1 of column k */
+        /* pivot search over rows k .. k1-1 of column k, then, if needed, over
+         * every row k .. N-1 */
+        const int k1 = pivot_tile_end(k, N, tile);
         double best = fabs(a[k][k]);
         double pv = a[k][k];
         int p = k;
         static_for<k + 1, N>(LUPP_SF(ic) {
             constexpr int i = decltype(ic)::value;
             const double v = fabs(a[k][i]);
-            const bool gt = v > best;
+            const bool gt = (i < k1) & (v > best);
             best = gt ? v : best;
             pv = gt ? a[k][i] : pv;
             p = gt ? i : p;
         });
+        if (tile > 0 && __ballot(best < thresh) != 0) {
+            const bool wide = best < thresh;
+            double bw = fabs(a[k][k]);
+            double pw = a[k][k];
+            int qw = k;
+            static_for<k + 1, N>(LUPP_SF(ic) {
+                constexpr int i = decltype(ic)::value;
+                const double v = fabs(a[k][i]);
+                const bool gt = v > bw;
+                bw = gt ? v : bw;
+                pw = gt ? a[k][i] : pw;
+                qw = gt ? i : qw;
+            });
+            best = wide ? bw : best;
+            pv = wide ? pw : pv;
+            p = wide ? qw : p;
+        }
         ipiv[k] = p + 1;
         const bool zero = (pv == 0.0);
         info = (zero && info == 0) ? k + 1 : info;
@@ -327,24 +363,45 @@ __device__ __forceinline__ int segment_min(int v)
 template <int N, int T, int k>
 __device__ __forceinline__ int lanes_pivot_owner(const double (&a)[(N + T - 1) / T][N],
                                                  const int (&pos)[(N + T - 1) / T], int seg_base,
-                                                 double &M, int &lpos, int &ls)
+                                                 double &M, int &lpos, int &ls, int tile,
+                                                 double thresh)
 {
     constexpr int K = lanes_shape<N, T>::K;
     const unsigned lowmask = T >= 32 ? 0xffffffffu : ((1u << (T & 31)) - 1u);
-    /* local candidate: largest |a_rk| among rows with pos >= k, lowest pos on ties */
-    double mag = -1.0;
-    lpos = 0x7fffffff;
-    ls = 0;
-    static_for<0, K>(LUPP_SF(sc) {
-        constexpr int s = decltype(sc)::value;
-        const double v = fabs(a[s][k]);
-        /* non-short-circuit logic: selects, not branches */
-        const bool take = (pos[s] >= k) & ((v > mag) | ((v == mag) & (pos[s] < lpos)));
-        mag = take ? v : mag;
-        lpos = take ? pos[s] : lpos;
-        ls = take ? s : ls;
-    });
+    /* local candidate: largest |a_rk| among rows with k <= pos < k1, lowest
+     * pos on ties; k1 = N unless the pivoting is tile-local */
+    const int k1 = pivot_tile_end(k, N, tile);
+    auto local_best = [&](int hi, double &mag, int &lp, int &sl) __attribute__((always_inline)) {
+        mag = -1.0;
+        lp = 0x7fffffff;
+        sl = 0;
+        static_for<0, K>(LUPP_SF(sc) {
+            constexpr int s = decltype(sc)::value;
+            const double v = fabs(a[s][k]);
+            /* non-short-circuit logic: selects, not branches */
+            const bool take = (pos[s] >= k) & (pos[s] < hi) &
+                              ((v > mag) | ((v == mag) & (pos[s] < lp)));
+            mag = take ? v : mag;
+            lp = take ? pos[s] : lp;
+            sl = take ? s : sl;
+        });
+    };
+    double mag;
+    local_best(k1, mag, lpos, ls);
     M = segment_max<T>(mag);
+    if (tile > 0 && __ballot(M < thresh) != 0) {
+        /* tile-local pivoting: segments whose in-tile best is below the
+         * threshold search every remaining row */
+        const bool wide = M < thresh;
+        double mw;
+        int lw, sw;
+        local_best(N, mw, lw, sw);
+        const double Mw = segment_max<T>(mw);
+        mag = wide ? mw : mag;
+        lpos = wide ? lw : lpos;
+        ls = wide ? sw : ls;
+        M = wide ? Mw : M;
+    }
     const uint64_t hits = __ballot(mag == M);
     const unsigned sb = (unsigned)(hits >> (unsigned)seg_base) & lowmask;
     /* sb != 0 for finite data; lane 0 keeps the owner inside the segment
@@ -409,12 +466,15 @@ __device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) /
  *
  * The pivot row reaches the other lanes of the segment by ds_bpermute, and
  * the trailing update runs under the exec mask of the trailing rows
- * (pos > k). No LDS allocation is needed. */
+ * (pos > k). No LDS allocation is needed. lanes_getrf_solve_x also calls
+ * x_sink(j, x_j) in every lane for every solution entry; tile / thresh
+ * select the pivoting rule (see thread_getrf_solve). */
 template <int N, int T, typename IpivSink, typename XSink>
-__device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N],
-                                                 double (&b)[(N + T - 1) / T],
-                                                 int (&pos)[(N + T - 1) / T], int seg_base,
-                                                 IpivSink ipiv_k, XSink x_sink)
+__device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][N],
+                                                   double (&b)[(N + T - 1) / T],
+                                                   int (&pos)[(N + T - 1) / T], int seg_base,
+                                                   IpivSink ipiv_k, XSink x_sink, int tile = 0,
+                                                   double thresh = 0.0)
 {
     constexpr int K = lanes_shape<N, T>::K;
     constexpr int CH = 8; /* pivot-row columns broadcast per chunk */
@@ -424,7 +484,7 @@ __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N]
         constexpr int k = decltype(kc)::value;
         double M;
         int lpos, ls;
-        const int tp = lanes_pivot_owner<N, T, k>(a, pos, seg_base, M, lpos, ls);
+        const int tp = lanes_pivot_owner<N, T, k>(a, pos, seg_base, M, lpos, ls, tile, thresh);
         const int src = seg_base + tp;
         const int ql = bcast_i32((lpos << 8) | ls, src);
         const int q = ql >> 8;  /* current position of the pivot row */
@@ -500,9 +560,9 @@ template <int N, int T, typename IpivSink>
 __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N],
                                                  double (&b)[(N + T - 1) / T],
                                                  int (&pos)[(N + T - 1) / T], int seg_base,
-                                                 IpivSink ipiv_k)
+                                                 IpivSink ipiv_k, int tile = 0, double thresh = 0.0)
 {
-    return lanes_getrf_solve<N, T>(a, b, pos, seg_base, ipiv_k, [](int, double) {});
+    return lanes_getrf_solve_x<N, T>(a, b, pos, seg_base, ipiv_k, [](int, double) {}, tile, thresh);
 }
 
 }  // namespace lupp

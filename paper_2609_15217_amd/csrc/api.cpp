@@ -27,6 +27,8 @@ struct lupp_ctx {
     lupp::BnWs *bn_ws = nullptr;         /* device workspace of the batched Newton */
     int newton_lanes[2] = {lupp::newton_default_lanes(LUPP_LAW_NORTON7),
                            lupp::newton_default_lanes(LUPP_LAW_NORTON_AF13)};
+    int tile = 0;          /* pivoting of lupp_batched_solve: 0 textbook, else tile-local */
+    double thresh = 0.0;
 };
 
 namespace lupp {
@@ -196,7 +198,7 @@ int lupp_batched_solve(lupp_ctx *ctx, int n, int64_t batch, int layout, double *
     int cur = 0;
     hipGetDevice(&cur);
     if (cur != ctx->device) hipSetDevice(ctx->device);
-    SolveArgs a{batch, A, lda, strideA, b, strideB, ipiv, info};
+    SolveArgs a{batch, A, lda, strideA, b, strideB, ipiv, info, ctx->tile, ctx->thresh};
     const hipError_t e = fn(a, layout, (flags & LUPP_KEEP_A) == 0, c.wpb, (hipStream_t)stream);
     if (cur != ctx->device) hipSetDevice(cur);
     return hip_err(e);
@@ -270,7 +272,7 @@ int lupp_autotune(lupp_ctx *ctx, int n, int64_t batch, int layout, const double 
         for (int i = 0; i < nw; ++i)
             cands[nc++] = {LUPP_VARIANT_LANES, widths[i], layout == LUPP_SOA ? 0 : w};
     }
-    SolveArgs a{batch, wA, lda, strideA, wB, strideB, wP, wI};
+    SolveArgs a{batch, wA, lda, strideA, wB, strideB, wP, wI, ctx->tile, ctx->thresh};
     for (int c = 0; c < nc && rc == 0; ++c) {
         if (!fits_offsets(n, batch, layout, cands[c].variant, cands[c].lanes, strideA, strideB))
             continue;
@@ -357,6 +359,24 @@ int constitutive_update(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *l
     const int rc = constitutive_launch(pts, law, tol, maxit, lanes, (hipStream_t)stream);
     if (cur != ctx->device) hipSetDevice(cur);
     return rc;
+}
+
+int lupp_set_pivoting(lupp_ctx *ctx, int tile, double threshold)
+{
+    if (ctx == nullptr) return -1;
+    if (tile < 0 || tile > 32) return -2;
+    if (!(threshold >= 0.0)) return -3;
+    ctx->tile = tile;
+    ctx->thresh = tile > 0 ? threshold : 0.0;
+    return 0;
+}
+
+int lupp_get_pivoting(const lupp_ctx *ctx, int *tile, double *threshold)
+{
+    if (ctx == nullptr) return -1;
+    if (tile) *tile = ctx->tile;
+    if (threshold) *threshold = ctx->thresh;
+    return 0;
 }
 
 int lupp_set_newton_variant(lupp_ctx *ctx, int kind, int lanes)

@@ -134,8 +134,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
         });
         /* x += dx as the back substitution hands out each dx_j (a zero pivot
          * skips the substitution, so y is then unchanged) */
-        const int inf = lanes_getrf_solve<NU, T>(a, b, pos, g * T, [](int, int) {},
-                                                 [&](int j, double x) { y[j] = y[j] + x; });
+        const int inf = lanes_getrf_solve_x<NU, T>(a, b, pos, g * T, [](int, int) {},
+                                                   [&](int j, double x) { y[j] = y[j] + x; });
         if (inf != 0) { status = 2; break; }
     }
 

@@ -19,6 +19,8 @@ struct SolveArgs {
     int64_t sB;  /* AoS: system stride; SoA: component stride */
     int32_t *ipiv;
     int32_t *info;
+    int tile;      /* pivoting rule: 0 textbook, >= 1 tile-local with this tile */
+    double thresh; /* tile-local acceptance threshold */
 };
 
 /* Enqueue one batched-solve kernel: layout LUPP_AOS/LUPP_SOA, factors =

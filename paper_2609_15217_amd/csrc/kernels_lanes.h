@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(256) k_lanes(SolveArgs a, int layout, int fact
             constexpr int cc = decltype(sc)::value;
             if (cc == c) pv[cc] = (t == k % T) ? v : pv[cc];
         });
-    });
+    }, a.tile, a.thresh);
 
     baseA = opaque_ptr(baseA);
     baseB = opaque_ptr(baseB);

@@ -171,7 +171,7 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
             constexpr int cc = decltype(sc)::value;
             if (cc == c) pv[cc] = (t == k % T) ? val : pv[cc];
         });
-    });
+    }, a.tile, a.thresh);
 
     /* ---------------------------------------------------------- store */
     baseA = opaque_ptr(baseA);

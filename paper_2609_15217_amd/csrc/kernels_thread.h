@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(256)
         });
     }
 
-    const int inf = thread_getrf_solve<N, true>(m, x, piv);
+    const int inf = thread_getrf_solve<N, true>(m, x, piv, a.tile, a.thresh);
 
     bA = opaque_ptr(bA);
     bB = opaque_ptr(bB);

@@ -131,7 +131,7 @@ EXPORTED = ["lupp_create", "lupp_destroy", "lupp_batched_solve", "lupp_batched_s
             "lupp_server_poll", "lupp_server_wait", "lupp_server_get_stats",
             "lupp_server_reset_stats", "lupp_sweep_create", "lupp_sweep_launch",
             "lupp_sweep_destroy", "constitutive_update_batched", "lupp_set_newton_variant",
-            "lupp_get_newton_variant"]
+            "lupp_get_newton_variant", "lupp_set_pivoting", "lupp_get_pivoting"]
 
 
 class LuppError(RuntimeError):
@@ -257,6 +257,21 @@ def constitutive_update(ctx: Context, pts: lupp_points, law: lupp_law, tol: floa
                         stream=None) -> int:
     return _constitutive_update(ctx.handle, ctypes.byref(pts), ctypes.byref(law), tol, maxit,
                                 _stream(stream))
+
+
+_lupp_set_pivoting = _sig("lupp_set_pivoting", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double])
+_lupp_get_pivoting = _sig("lupp_get_pivoting", ctypes.c_int,
+                          [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)])
+
+
+def lupp_set_pivoting(ctx: Context, tile: int, threshold: float = 1e-10) -> int:
+    return _lupp_set_pivoting(ctx.handle, tile, threshold)
+
+
+def lupp_get_pivoting(ctx: Context):
+    t, th = ctypes.c_int(0), ctypes.c_double(0.0)
+    rc = _lupp_get_pivoting(ctx.handle, ctypes.byref(t), ctypes.byref(th))
+    return rc, t.value, th.value
 
 
 _lupp_set_newton_variant = _sig("lupp_set_newton_variant", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int])
