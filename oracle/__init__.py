@@ -59,9 +59,10 @@ def lib():
         L.oracle_gesv_batch.argtypes = [ctypes.c_int, i64, P, ctypes.c_int, i64, P, i64, P, P, P,
                                         ctypes.c_int]
         L.oracle_gesv_batch.restype = None
-        L.oracle_gesv_batch_tiled.argtypes = [ctypes.c_int, i64, P, ctypes.c_int, i64, P, i64, P,
-                                              P, ctypes.c_int, ctypes.c_double, P, ctypes.c_int]
-        L.oracle_gesv_batch_tiled.restype = None
+        L.oracle_gesv_batch_mode.argtypes = [ctypes.c_int, i64, P, ctypes.c_int, i64, P, i64, P,
+                                             P, ctypes.c_int, ctypes.c_double, ctypes.c_int, P,
+                                             ctypes.c_int]
+        L.oracle_gesv_batch_mode.restype = None
         L.oracle_gesv_ragged.argtypes = [i64, P, P, P, P, P, P, P, ctypes.c_int]
         L.oracle_gesv_ragged.restype = None
         L.oracle_law_eval.argtypes = [P, P, P, P, P, P, P]
@@ -125,19 +126,27 @@ def gesv_batch(A: np.ndarray, b: np.ndarray, threads: int | None = None, want_ga
     return out
 
 
-def gesv_batch_tiled(A: np.ndarray, b: np.ndarray, tile: int, thresh: float = 1e-10,
-                     threads: int | None = None):
-    """Batched dgesv with tile-local pivoting (tile size `tile`, acceptance
-    threshold `thresh`). Returns dict(LU, x, ipiv, info, out_of_tile)."""
+def gesv_batch_mode(A: np.ndarray, b: np.ndarray, tile: int = 0, thresh: float = 1e-10,
+                    fma: bool = False, threads: int | None = None):
+    """Batched dgesv under a pivoting rule (tile 0: textbook; else tile-local
+    with acceptance threshold `thresh`) and arithmetic mode (fma: every
+    multiply-subtract fused). Returns dict(LU, x, ipiv, info, out_of_tile)."""
     a = _f64(A).copy()
     x = _f64(b).copy()
     batch, n = a.shape[0], a.shape[1]
     ipiv = np.zeros((batch, n), dtype=np.int32)
     info = np.zeros(batch, dtype=np.int32)
     oot = np.zeros(batch, dtype=np.int32)
-    lib().oracle_gesv_batch_tiled(n, batch, _p(a), n, n * n, _p(x), n, _p(ipiv), _p(info), tile,
-                                  thresh, _p(oot), threads or default_threads())
+    lib().oracle_gesv_batch_mode(n, batch, _p(a), n, n * n, _p(x), n, _p(ipiv), _p(info), tile,
+                                 thresh if tile else 0.0, 1 if fma else 0, _p(oot),
+                                 threads or default_threads())
     return {"LU": a, "x": x, "ipiv": ipiv, "info": info, "out_of_tile": oot}
+
+
+def gesv_batch_tiled(A: np.ndarray, b: np.ndarray, tile: int, thresh: float = 1e-10,
+                     threads: int | None = None):
+    """Batched dgesv with tile-local pivoting (strict arithmetic)."""
+    return gesv_batch_mode(A, b, tile, thresh, False, threads)
 
 
 def gesv_ragged(n: np.ndarray, offA: np.ndarray, offB: np.ndarray, A: np.ndarray,

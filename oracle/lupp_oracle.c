@@ -20,6 +20,13 @@
 /* stored below the diagonal, and the trailing submatrix (Schur complement)  */
 /* receives a_ij <- a_ij - l_ik * u_kj.                                      */
 /* ------------------------------------------------------------------------ */
+/* a - l*u as one rounded multiply and one rounded subtract (strict mode), or
+ * as one fused multiply-add (FMA mode). */
+static inline double oracle_msub(double a, double l, double u, int use_fma)
+{
+    return use_fma ? fma(-l, u, a) : a - l * u;
+}
+
 /* Index of the first largest |col[i]| over lo <= i < hi (lowest row on ties). */
 static int oracle_argmax_abs(const double *col, int lo, int hi)
 {
@@ -41,7 +48,7 @@ static int oracle_argmax_abs(const double *col, int lo, int hi)
  * k); only if the best of them is below thresh in magnitude does the search
  * extend to every row k .. n-1 (counted in *oot). */
 static int oracle_getrf_rule(int n, double *a, int lda, int32_t *ipiv, double *gap, int ts,
-                             double thresh, int *oot)
+                             double thresh, int use_fma, int *oot)
 {
     int info = 0;
     double g = 1.0;
@@ -86,8 +93,8 @@ static int oracle_getrf_rule(int n, double *a, int lda, int32_t *ipiv, double *g
             a[i + (int64_t)k * lda] = a[i + (int64_t)k * lda] / a[k + (int64_t)k * lda];
         for (int j = k + 1; j < n; ++j)
             for (int i = k + 1; i < n; ++i)
-                a[i + (int64_t)j * lda] =
-                    a[i + (int64_t)j * lda] - a[i + (int64_t)k * lda] * a[k + (int64_t)j * lda];
+                a[i + (int64_t)j * lda] = oracle_msub(a[i + (int64_t)j * lda], a[i + (int64_t)k * lda],
+                                                      a[k + (int64_t)j * lda], use_fma);
     }
     if (gap != NULL) *gap = g;
     return info;
@@ -95,20 +102,21 @@ static int oracle_getrf_rule(int n, double *a, int lda, int32_t *ipiv, double *g
 
 int oracle_getrf(int n, double *a, int lda, int32_t *ipiv, double *gap)
 {
-    return oracle_getrf_rule(n, a, lda, ipiv, gap, 0, 0.0, NULL);
+    return oracle_getrf_rule(n, a, lda, ipiv, gap, 0, 0.0, 0, NULL);
 }
 
 int oracle_getrf_tiled(int n, double *a, int lda, int32_t *ipiv, int ts, double thresh,
                        int *out_of_tile)
 {
     if (out_of_tile != NULL) *out_of_tile = 0;
-    return oracle_getrf_rule(n, a, lda, ipiv, NULL, ts, thresh, out_of_tile);
+    return oracle_getrf_rule(n, a, lda, ipiv, NULL, ts, thresh, 0, out_of_tile);
 }
 
 /* Triangular solves (Section 2.2): apply the interchanges to b, then L y = P b
  * (unit lower, column by column, ascending), then U x = y (column by column,
  * descending: divide by the diagonal, then eliminate the column above it). */
-void oracle_getrs(int n, const double *lu, int lda, const int32_t *ipiv, double *b)
+static void oracle_getrs_mode(int n, const double *lu, int lda, const int32_t *ipiv, double *b,
+                              int use_fma)
 {
     for (int k = 0; k < n; ++k) {
         int p = ipiv[k] - 1;
@@ -120,12 +128,17 @@ void oracle_getrs(int n, const double *lu, int lda, const int32_t *ipiv, double 
     }
     for (int j = 0; j < n; ++j)
         for (int i = j + 1; i < n; ++i)
-            b[i] = b[i] - lu[i + (int64_t)j * lda] * b[j];
+            b[i] = oracle_msub(b[i], lu[i + (int64_t)j * lda], b[j], use_fma);
     for (int j = n - 1; j >= 0; --j) {
         b[j] = b[j] / lu[j + (int64_t)j * lda];
         for (int i = 0; i < j; ++i)
-            b[i] = b[i] - lu[i + (int64_t)j * lda] * b[j];
+            b[i] = oracle_msub(b[i], lu[i + (int64_t)j * lda], b[j], use_fma);
     }
+}
+
+void oracle_getrs(int n, const double *lu, int lda, const int32_t *ipiv, double *b)
+{
+    oracle_getrs_mode(n, lu, lda, ipiv, b, 0);
 }
 
 int oracle_gesv(int n, double *a, int lda, double *b, int32_t *ipiv, double *gap)
@@ -195,33 +208,34 @@ static void batch_body(void *p, int64_t lo, int64_t hi)
 }
 
 typedef struct {
-    int n, lda, ts;
+    int n, lda, ts, use_fma;
     double thresh;
     int64_t strideA, strideB;
     double *a, *b;
     int32_t *ipiv, *info, *oot;
-} tiled_ctx;
+} rule_ctx;
 
-static void tiled_body(void *p, int64_t lo, int64_t hi)
+static void rule_body(void *p, int64_t lo, int64_t hi)
 {
-    tiled_ctx *c = (tiled_ctx *)p;
+    rule_ctx *c = (rule_ctx *)p;
     for (int64_t s = lo; s < hi; ++s) {
         int oot = 0;
         double *a = c->a + s * c->strideA;
         int32_t *ipiv = c->ipiv + s * c->n;
-        const int info = oracle_getrf_tiled(c->n, a, c->lda, ipiv, c->ts, c->thresh, &oot);
-        if (info == 0) oracle_getrs(c->n, a, c->lda, ipiv, c->b + s * c->strideB);
+        const int info =
+            oracle_getrf_rule(c->n, a, c->lda, ipiv, NULL, c->ts, c->thresh, c->use_fma, &oot);
+        if (info == 0) oracle_getrs_mode(c->n, a, c->lda, ipiv, c->b + s * c->strideB, c->use_fma);
         c->info[s] = info;
         if (c->oot) c->oot[s] = oot;
     }
 }
 
-void oracle_gesv_batch_tiled(int n, int64_t batch, double *a, int lda, int64_t strideA,
-                             double *b, int64_t strideB, int32_t *ipiv, int32_t *info, int ts,
-                             double thresh, int32_t *out_of_tile, int nthreads)
+void oracle_gesv_batch_mode(int n, int64_t batch, double *a, int lda, int64_t strideA,
+                            double *b, int64_t strideB, int32_t *ipiv, int32_t *info, int ts,
+                            double thresh, int use_fma, int32_t *out_of_tile, int nthreads)
 {
-    tiled_ctx c = {n, lda, ts, thresh, strideA, strideB, a, b, ipiv, info, out_of_tile};
-    oracle_parallel_for(batch, nthreads, tiled_body, &c);
+    rule_ctx c = {n, lda, ts, use_fma, thresh, strideA, strideB, a, b, ipiv, info, out_of_tile};
+    oracle_parallel_for(batch, nthreads, rule_body, &c);
 }
 
 void oracle_gesv_batch(int n, int64_t batch, double *a, int lda, int64_t strideA,

@@ -54,10 +54,16 @@ void oracle_gesv_batch(int n, int64_t batch, double *a, int lda, int64_t strideA
  * oracle_getrs. ts <= 0 or ts >= n is textbook partial pivoting. */
 int oracle_getrf_tiled(int n, double *a, int lda, int32_t *ipiv, int ts, double thresh,
                        int *out_of_tile);
-/* Batched tiled dgesv (AoS, as oracle_gesv_batch); out_of_tile[batch] or NULL. */
-void oracle_gesv_batch_tiled(int n, int64_t batch, double *a, int lda, int64_t strideA,
-                             double *b, int64_t strideB, int32_t *ipiv, int32_t *info, int ts,
-                             double thresh, int32_t *out_of_tile, int nthreads);
+/* Batched dgesv (AoS, as oracle_gesv_batch) under a chosen pivoting rule
+ * (ts, thresh as oracle_getrf_tiled; ts = 0 textbook) and arithmetic mode:
+ * use_fma = 0 is strict (every multiply-subtract a - l*u of the elimination
+ * and of both substitutions rounds the product and then the difference),
+ * use_fma = 1 computes each of them as one fused multiply-add fma(-l, u, a);
+ * multipliers and diagonal divisions are true divisions in both modes.
+ * out_of_tile[batch] or NULL. */
+void oracle_gesv_batch_mode(int n, int64_t batch, double *a, int lda, int64_t strideA,
+                            double *b, int64_t strideB, int32_t *ipiv, int32_t *info, int ts,
+                            double thresh, int use_fma, int32_t *out_of_tile, int nthreads);
 
 /* Ragged batch: system s has size n[s], matrix at a + offA[s] (lda = n[s]),
  * right-hand side and pivots at offset offB[s]. */

@@ -16,10 +16,12 @@ SRC = os.path.join(ROOT, "oracle", "lupp_oracle.c")
 
 MUTANTS = {
     "tie_break_highest_row": ("if (v > best) {", "if (v >= best) {"),
-    "update_sign": ("a[i + (int64_t)j * lda] - a[i + (int64_t)k * lda] * a[k + (int64_t)j * lda]",
-                    "a[i + (int64_t)j * lda] + a[i + (int64_t)k * lda] * a[k + (int64_t)j * lda]"),
-    "update_transposed": ("a[i + (int64_t)k * lda] * a[k + (int64_t)j * lda];",
-                          "a[i + (int64_t)k * lda] * a[j + (int64_t)k * lda];"),
+    "update_sign": ("return use_fma ? fma(-l, u, a) : a - l * u;",
+                    "return use_fma ? fma(-l, u, a) : a + l * u;"),
+    "fma_update_sign": ("return use_fma ? fma(-l, u, a) : a - l * u;",
+                        "return use_fma ? fma(l, u, a) : a - l * u;"),
+    "update_transposed": ("a[k + (int64_t)j * lda], use_fma);",
+                          "a[j + (int64_t)k * lda], use_fma);"),
     "swap_trailing_only": ("for (int j = 0; j < n; ++j) {\n                double t = a[k + (int64_t)j * lda];",
                            "for (int j = k; j < n; ++j) {\n                double t = a[k + (int64_t)j * lda];"),
     "no_rhs_interchange": ("int p = ipiv[k] - 1;", "int p = k;"),
@@ -54,6 +56,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_lupp.py"),
                         os.path.join(ROOT, "tests", "test_oracle_newton.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_tiled.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_tiled.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_fma.py")],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
