@@ -270,12 +270,13 @@ def main():
             wA.copy_(pA)
             wb.copy_(pb)
 
-    def launch(key):
+    def launch(key, flags=0):
         n, lay = key
         wA, wb, ipiv, info = work[key]
         layout = L.LUPP_SOA if lay == "soa" else L.LUPP_AOS
         sA, sB = (BATCH, BATCH) if lay == "soa" else (n * n, n)
-        rc = L.lupp_batched_solve(ctx, n, BATCH, layout, wA, n, sA, wb, sB, ipiv, info, 0, stream)
+        rc = L.lupp_batched_solve(ctx, n, BATCH, layout, wA, n, sA, wb, sB, ipiv, info, flags,
+                                  stream)
         if rc != 0:
             raise RuntimeError(f"lupp_batched_solve n={n} {lay}: {L.lupp_error_string(rc)}")
 
@@ -367,6 +368,28 @@ def main():
             tiled[f"n{k[0]}_{k[1]}"] = {"ms": round(float(np.mean(tt)), 4), "textbook_ms": base}
         assert L.lupp_set_pivoting(ctx, 0, 0.0) == 0
         log(f"tile-local pivoting: {tiled}")
+
+    # ------------------------------------------------------------- FMA mode
+    # the same sweep kernels with every multiply-subtract fused (LUPP_FMA)
+    fma_mode = {}
+    if not args.only:
+        for k in keys:
+            tt = []
+            for r in range(args.warmup + min(args.steps, 3)):
+                restore()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                launch(k, L.LUPP_FMA)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if r >= args.warmup:
+                    tt.append(e0.elapsed_time(e1))
+            base = next(r for r in per_kernel if (r["n"], r["layout"]) == k)["ms"]
+            fma_mode[f"n{k[0]}_{k[1]}"] = {"ms": round(float(np.mean(tt)), 4), "strict_ms": base}
+        fma_total = sum(v["ms"] for v in fma_mode.values())
+        fma_mode["sweep_systems_per_s"] = round(len(keys) * BATCH / (fma_total * 1e-3))
+        log(f"FMA mode: {fma_mode}")
 
     # ------------------------------------------------------------- ragged
     ragged = {}
@@ -625,6 +648,7 @@ def main():
         "newton": newton,
         "sweep": sweep,
         "tile_local_pivoting": tiled,
+        "fma_mode": fma_mode,
         "ragged": ragged,
         "serving": serving,
         "latency": lat,

@@ -49,9 +49,12 @@ extern "C" {
 /* Flags. LUPP_KEEP_A: do not write the factors back (A is left unchanged).
  * LUPP_RAGGED_PER_SIZE (lupp_batched_solve_ragged only): instead of the one
  * persistent launch, read the size histogram back to the host and launch one
- * kernel per size (the plain baseline; it synchronises the stream). */
+ * kernel per size (the plain baseline; it synchronises the stream).
+ * LUPP_FMA (lupp_batched_solve only): fused multiply-add arithmetic, see
+ * lupp_batched_solve. */
 #define LUPP_KEEP_A 1u
 #define LUPP_RAGGED_PER_SIZE 2u
+#define LUPP_FMA 4u
 
 /* Kernel variants (for lupp_force_variant and lupp_variant_info). */
 #define LUPP_VARIANT_AUTO 0
@@ -92,7 +95,12 @@ int lupp_get_device(const lupp_ctx *ctx, int *device);
  *             rows k+1 and r were exchanged at step k; r >= k+1.
  *   info    : int32 per system: 0, or k+1 for the first step k whose pivot
  *             is exactly zero (the factorisation still completes).
- *   flags   : 0 or LUPP_KEEP_A.
+ *   flags   : 0, LUPP_KEEP_A, LUPP_FMA, or both. LUPP_FMA: FMA arithmetic -
+ *             every multiply-subtract of the elimination and of both
+ *             substitutions is one fused multiply-add (divisions and pivoting
+ *             as in strict mode); results are then bitwise those of the
+ *             oracle's FMA mode rather than of the strict default. Not
+ *             combined with tile-local pivoting (LUPP_E_UNSUPPORTED).
  * Inputs containing NaN or Inf produce unspecified factors and info. */
 int lupp_batched_solve(lupp_ctx *ctx, int n, int64_t batch, int layout, double *A, int64_t lda,
                        int64_t strideA, double *b, int64_t strideB, int32_t *ipiv,

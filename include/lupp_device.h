@@ -21,6 +21,10 @@
  * the textbook algorithm, so results are bitwise reproducible across thread
  * and lanes mappings, layouts, batch compositions and launches. Translation
  * units that use this header must be compiled with -ffp-contract=off.
+ * FMA mode (the solvers' kFMA parameter): every multiply-subtract of the
+ * elimination and of both substitutions is one fused multiply-add instead;
+ * divisions and pivoting are unchanged, so the results are again the same
+ * for every mapping (and differ from strict mode in the last bits).
  *
  * info: 0, or k+1 for the first step k whose pivot is exactly zero (the
  * factorisation still completes; the solution is then not computed).
@@ -74,6 +78,15 @@ __device__ __forceinline__ void static_for_down(F &&f)
 
 #define LUPP_SF(v) [&](auto v) __attribute__((always_inline))
 
+/* a - l*u: in strict mode one rounded multiply then one rounded subtract;
+ * with kFMA one fused multiply-add (fma(-l, u, a), a single rounding). */
+template <bool kFMA>
+__device__ __forceinline__ double msub(double a, double l, double u)
+{
+    if constexpr (kFMA) return __builtin_fma(-l, u, a);
+    else return a - l * u;
+}
+
 /* Last row + 1 of the pivot candidates tried first at step k: the end of the
  * diagonal tile of size `tile` holding k (tile-local pivoting, the Tiled
  * solvers' rule, Section 3.2.2), or n for textbook partial pivoting
@@ -85,12 +98,13 @@ __device__ __forceinline__ int pivot_tile_end(int k, int n, int tile)
     return e < n ? e : n;
 }
 
-/* Pivoting rule (all solvers): tile <= 0 is textbook partial pivoting (the
- * default). tile >= 1 is tile-local pivoting: the candidates at step k are
- * first the rows k .. pivot_tile_end - 1, and only if the best of them has
- * magnitude below `thresh` are all rows k .. n-1 searched; ties go to the
- * lowest row (position) either way. */
-template <int N, bool kFactors>
+/* Pivoting rule (all solvers): textbook partial pivoting unless the kTile
+ * parameter is set (then tile >= 1 is required): tile-local pivoting, where
+ * the candidates at step k are first the rows k .. pivot_tile_end - 1, and
+ * only if the best of them has magnitude below `thresh` are all rows
+ * k .. n-1 searched; ties go to the lowest row (position) either way.
+ * Without kTile the solvers contain no tile code at all. */
+template <int N, bool kFactors, bool kFMA = false, bool kTile = false>
 __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)[N],
                                                   int (&ipiv)[N], int tile = 0,
                                                   double thresh = 0.0)
@@ -100,19 +114,20 @@ __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)
         constexpr int k = decltype(kc)::value;
         /* pivot search over rows k .. k1-1 of column k, then, if needed, over
          * every row k .. N-1 */
-        const int k1 = pivot_tile_end(k, N, tile);
+        const int k1 = kTile ? pivot_tile_end(k, N, tile) : N;
         double best = fabs(a[k][k]);
         double pv = a[k][k];
         int p = k;
         static_for<k + 1, N>(LUPP_SF(ic) {
             constexpr int i = decltype(ic)::value;
             const double v = fabs(a[k][i]);
-            const bool gt = (i < k1) & (v > best);
+            bool gt = v > best;
+            if constexpr (kTile) gt = gt & (i < k1);
             best = gt ? v : best;
             pv = gt ? a[k][i] : pv;
             p = gt ? i : p;
         });
-        if (tile > 0 && __ballot(best < thresh) != 0) {
+        if (kTile && __ballot(best < thresh) != 0) {
             const bool wide = best < thresh;
             double bw = fabs(a[k][k]);
             double pw = a[k][k];
@@ -172,12 +187,12 @@ __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)
                 constexpr int j = decltype(jc)::value;
                 static_for<k + 1, N>(LUPP_SF(ic) {
                     constexpr int i = decltype(ic)::value;
-                    a[j][i] = a[j][i] - a[k][i] * a[j][k];
+                    a[j][i] = msub<kFMA>(a[j][i], a[k][i], a[j][k]);
                 });
             });
             static_for<k + 1, N>(LUPP_SF(ic) {
                 constexpr int i = decltype(ic)::value;
-                b[i] = b[i] - a[k][i] * b[k];
+                b[i] = msub<kFMA>(b[i], a[k][i], b[k]);
             });
         }
     });
@@ -187,7 +202,7 @@ __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)
             b[j] = b[j] / a[j][j];
             static_for<0, j>(LUPP_SF(ic) {
                 constexpr int i = decltype(ic)::value;
-                b[i] = b[i] - a[j][i] * b[j];
+                b[i] = msub<kFMA>(b[i], a[j][i], b[j]);
             });
         });
     }
@@ -360,7 +375,7 @@ __device__ __forceinline__ int segment_min(int v)
  * a second reduction pick the lowest position. Returns the owner's lane
  * within the segment; lpos / ls are this lane's best candidate position and
  * slot (meaningful in the owner). */
-template <int N, int T, int k>
+template <int N, int T, int k, bool kTile>
 __device__ __forceinline__ int lanes_pivot_owner(const double (&a)[(N + T - 1) / T][N],
                                                  const int (&pos)[(N + T - 1) / T], int seg_base,
                                                  double &M, int &lpos, int &ls, int tile,
@@ -370,32 +385,38 @@ __device__ __forceinline__ int lanes_pivot_owner(const double (&a)[(N + T - 1) /
     const unsigned lowmask = T >= 32 ? 0xffffffffu : ((1u << (T & 31)) - 1u);
     /* local candidate: largest |a_rk| among rows with k <= pos < k1, lowest
      * pos on ties; k1 = N unless the pivoting is tile-local */
-    const int k1 = pivot_tile_end(k, N, tile);
-    auto local_best = [&](int hi, double &mag, int &lp, int &sl) __attribute__((always_inline)) {
+    /* in_tile: candidates also need pos < hi (tile-local pivoting); without
+     * it every row with pos >= k is a candidate */
+    auto local_best = [&](auto in_tile, int hi, double &mag, int &lp, int &sl)
+                          __attribute__((always_inline)) {
         mag = -1.0;
         lp = 0x7fffffff;
         sl = 0;
         static_for<0, K>(LUPP_SF(sc) {
             constexpr int s = decltype(sc)::value;
             const double v = fabs(a[s][k]);
+            bool cand = pos[s] >= k;
+            if constexpr (decltype(in_tile)::value) cand = cand & (pos[s] < hi);
             /* non-short-circuit logic: selects, not branches */
-            const bool take = (pos[s] >= k) & (pos[s] < hi) &
-                              ((v > mag) | ((v == mag) & (pos[s] < lp)));
+            const bool take = cand & ((v > mag) | ((v == mag) & (pos[s] < lp)));
             mag = take ? v : mag;
             lp = take ? pos[s] : lp;
             sl = take ? s : sl;
         });
     };
     double mag;
-    local_best(k1, mag, lpos, ls);
+    if constexpr (kTile)
+        local_best(std::true_type{}, pivot_tile_end(k, N, tile), mag, lpos, ls);
+    else
+        local_best(std::false_type{}, N, mag, lpos, ls);
     M = segment_max<T>(mag);
-    if (tile > 0 && __ballot(M < thresh) != 0) {
+    if (kTile && __ballot(M < thresh) != 0) {
         /* tile-local pivoting: segments whose in-tile best is below the
          * threshold search every remaining row */
         const bool wide = M < thresh;
         double mw;
         int lw, sw;
-        local_best(N, mw, lw, sw);
+        local_best(std::false_type{}, N, mw, lw, sw);
         const double Mw = segment_max<T>(mw);
         mag = wide ? mw : mag;
         lpos = wide ? lw : lpos;
@@ -424,7 +445,7 @@ __device__ __forceinline__ int lanes_pivot_owner(const double (&a)[(N + T - 1) /
  * lane of the segment sees every x_j: x_sink(j, x_j) is called by all lanes
  * (a solver whose callers need the whole solution in every lane gets it
  * without further communication). */
-template <int N, int T, typename XSink>
+template <int N, int T, bool kFMA, typename XSink>
 __device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) / T][N],
                                                  double (&b)[(N + T - 1) / T],
                                                  const int (&pos)[(N + T - 1) / T], int seg_base,
@@ -451,7 +472,7 @@ __device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) /
         static_for<0, K>(LUPP_SF(sc) {
             constexpr int s = decltype(sc)::value;
             if (pos[s] == j) b[s] = x;
-            else if (pos[s] >= 0 && pos[s] < j) b[s] = b[s] - a[s][j] * x;
+            else if (pos[s] >= 0 && pos[s] < j) b[s] = msub<kFMA>(b[s], a[s][j], x);
         });
     });
 }
@@ -469,7 +490,8 @@ __device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) /
  * (pos > k). No LDS allocation is needed. lanes_getrf_solve_x also calls
  * x_sink(j, x_j) in every lane for every solution entry; tile / thresh
  * select the pivoting rule (see thread_getrf_solve). */
-template <int N, int T, typename IpivSink, typename XSink>
+template <int N, int T, bool kFMA = false, bool kTile = false, typename IpivSink,
+          typename XSink>
 __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][N],
                                                    double (&b)[(N + T - 1) / T],
                                                    int (&pos)[(N + T - 1) / T], int seg_base,
@@ -484,7 +506,8 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
         constexpr int k = decltype(kc)::value;
         double M;
         int lpos, ls;
-        const int tp = lanes_pivot_owner<N, T, k>(a, pos, seg_base, M, lpos, ls, tile, thresh);
+        const int tp =
+            lanes_pivot_owner<N, T, k, kTile>(a, pos, seg_base, M, lpos, ls, tile, thresh);
         const int src = seg_base + tp;
         const int ql = bcast_i32((lpos << 8) | ls, src);
         const int q = ql >> 8;  /* current position of the pivot row */
@@ -538,31 +561,32 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
                     if (pos[s] > k) {
                         static_for<j0, j1>(LUPP_SF(jc) {
                             constexpr int j = decltype(jc)::value;
-                            a[s][j] = a[s][j] - l[s] * u[j - j0];
+                            a[s][j] = msub<kFMA>(a[s][j], l[s], u[j - j0]);
                         });
-                        if constexpr (decltype(cc)::value == 0) b[s] = b[s] - l[s] * y;
+                        if constexpr (decltype(cc)::value == 0) b[s] = msub<kFMA>(b[s], l[s], y);
                     }
                 });
             });
             if constexpr (k + 1 >= N) {
                 static_for<0, K>(LUPP_SF(sc) {
                     constexpr int s = decltype(sc)::value;
-                    if (pos[s] > k) b[s] = b[s] - l[s] * y;
+                    if (pos[s] > k) b[s] = msub<kFMA>(b[s], l[s], y);
                 });
             }
         }
     });
-    if (info == 0) lanes_back_subst<N, T>(a, b, pos, seg_base, x_sink);
+    if (info == 0) lanes_back_subst<N, T, kFMA>(a, b, pos, seg_base, x_sink);
     return info;
 }
 
-template <int N, int T, typename IpivSink>
+template <int N, int T, bool kFMA = false, bool kTile = false, typename IpivSink>
 __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N],
                                                  double (&b)[(N + T - 1) / T],
                                                  int (&pos)[(N + T - 1) / T], int seg_base,
                                                  IpivSink ipiv_k, int tile = 0, double thresh = 0.0)
 {
-    return lanes_getrf_solve_x<N, T>(a, b, pos, seg_base, ipiv_k, [](int, double) {}, tile, thresh);
+    return lanes_getrf_solve_x<N, T, kFMA, kTile>(a, b, pos, seg_base, ipiv_k, [](int, double) {},
+                                                  tile, thresh);
 }
 
 }  // namespace lupp

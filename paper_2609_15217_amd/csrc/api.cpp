@@ -174,7 +174,7 @@ int lupp_check_solve_args(int n, int64_t batch, int layout, const double *A, int
     if (layout == LUPP_AOS ? strideB < n : strideB < batch) return -9;
     if (ipiv == nullptr && batch > 0) return -10;
     if (info == nullptr && batch > 0) return -11;
-    if ((flags & ~LUPP_KEEP_A) != 0) return -12;
+    if ((flags & ~(LUPP_KEEP_A | LUPP_FMA)) != 0) return -12;
     return 0;
 }
 
@@ -188,6 +188,8 @@ int lupp_batched_solve(lupp_ctx *ctx, int n, int64_t batch, int layout, double *
     if (bad != 0) return bad;
     if (batch == 0) return 0;
 
+    /* compiled instances: strict, FMA, strict with tile-local pivoting */
+    if ((flags & LUPP_FMA) != 0 && ctx->tile > 0) return LUPP_E_UNSUPPORTED;
     Choice c = ctx->table[n][layout][bucket_of(batch)];
     if (ctx->forced_variant != LUPP_VARIANT_AUTO)
         c = Choice{ctx->forced_variant, ctx->forced_lanes, ctx->forced_wpb};
@@ -198,7 +200,8 @@ int lupp_batched_solve(lupp_ctx *ctx, int n, int64_t batch, int layout, double *
     int cur = 0;
     hipGetDevice(&cur);
     if (cur != ctx->device) hipSetDevice(ctx->device);
-    SolveArgs a{batch, A, lda, strideA, b, strideB, ipiv, info, ctx->tile, ctx->thresh};
+    SolveArgs a{batch, A, lda, strideA, b, strideB, ipiv, info, ctx->tile, ctx->thresh,
+                (flags & LUPP_FMA) != 0 ? 1 : 0};
     const hipError_t e = fn(a, layout, (flags & LUPP_KEEP_A) == 0, c.wpb, (hipStream_t)stream);
     if (cur != ctx->device) hipSetDevice(cur);
     return hip_err(e);
@@ -272,7 +275,7 @@ int lupp_autotune(lupp_ctx *ctx, int n, int64_t batch, int layout, const double 
         for (int i = 0; i < nw; ++i)
             cands[nc++] = {LUPP_VARIANT_LANES, widths[i], layout == LUPP_SOA ? 0 : w};
     }
-    SolveArgs a{batch, wA, lda, strideA, wB, strideB, wP, wI, ctx->tile, ctx->thresh};
+    SolveArgs a{batch, wA, lda, strideA, wB, strideB, wP, wI, ctx->tile, ctx->thresh, 0};
     for (int c = 0; c < nc && rc == 0; ++c) {
         if (!fits_offsets(n, batch, layout, cands[c].variant, cands[c].lanes, strideA, strideB))
             continue;

@@ -21,6 +21,7 @@ struct SolveArgs {
     int32_t *info;
     int tile;      /* pivoting rule: 0 textbook, >= 1 tile-local with this tile */
     double thresh; /* tile-local acceptance threshold */
+    int fma;       /* 1: fused multiply-add arithmetic (LUPP_FMA), 0: strict */
 };
 
 /* Enqueue one batched-solve kernel: layout LUPP_AOS/LUPP_SOA, factors =

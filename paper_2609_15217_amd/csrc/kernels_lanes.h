@@ -23,7 +23,7 @@
 
 namespace lupp {
 
-template <int N, int T>
+template <int N, int T, bool F, bool Tl>
 __global__ void __launch_bounds__(256) k_lanes(SolveArgs a, int layout, int factors)
 {
     constexpr int K = lanes_shape<N, T>::K;
@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(256) k_lanes(SolveArgs a, int layout, int fact
     constexpr int KP = (N + T - 1) / T;
     int pv[KP];
     static_for<0, KP>([&](auto sc) __attribute__((always_inline)) { pv[decltype(sc)::value] = 0; });
-    const int inf = lanes_getrf_solve<N, T>(m, x, pos, g * T, [&](int k, int v) {
+    const int inf = lanes_getrf_solve<N, T, F, Tl>(m, x, pos, g * T, [&](int k, int v) {
         const int c = k / T;
         static_for<0, KP>([&](auto sc) __attribute__((always_inline)) {
             constexpr int cc = decltype(sc)::value;
@@ -131,8 +131,17 @@ hipError_t launch_lanes(const SolveArgs &a, int layout, bool factors, int wpb, h
     const int w = wpb > 0 ? wpb : 4;
     const int64_t per_block = (int64_t)w * (64 / T);
     const int64_t blocks = (a.batch + per_block - 1) / per_block;
-    hipLaunchKernelGGL((k_lanes<N, T>), dim3((unsigned)blocks), dim3(64 * w), 0, st, a, layout,
-                       (int)factors);
+    /* arithmetic x pivoting instances: strict, FMA, strict + tile-local */
+    if (a.fma && a.tile > 0) return hipErrorNotSupported;
+    if (a.fma)
+        hipLaunchKernelGGL((k_lanes<N, T, true, false>), dim3((unsigned)blocks), dim3(64 * w), 0, st,
+                           a, layout, (int)factors);
+    else if (a.tile > 0)
+        hipLaunchKernelGGL((k_lanes<N, T, false, true>), dim3((unsigned)blocks), dim3(64 * w), 0, st,
+                           a, layout, (int)factors);
+    else
+        hipLaunchKernelGGL((k_lanes<N, T, false, false>), dim3((unsigned)blocks), dim3(64 * w), 0,
+                           st, a, layout, (int)factors);
     return hipGetLastError();
 }
 
@@ -145,8 +154,8 @@ hipError_t launch_lanes(const SolveArgs &a, int layout, bool factors, int wpb, h
     LaunchFn lanes_fn_##N##_##T() { return launch_lanes<N, T>; }                   \
     const void *lanes_sym_##N##_##T(int layout)                                    \
     {                                                                              \
-        return layout == LUPP_SOA ? reinterpret_cast<const void *>(&k_lanes_soa<N, T>) \
-                                  : reinterpret_cast<const void *>(&k_lanes<N, T>); \
+        return layout == LUPP_SOA ? reinterpret_cast<const void *>(&k_lanes_soa<N, T, false, false>) \
+                                  : reinterpret_cast<const void *>(&k_lanes<N, T, false, false>); \
     }                                                                              \
     }
 

@@ -62,7 +62,7 @@ __device__ __forceinline__ int soa_sw(int i)
     return ((i >> Sh::SH) << Sh::LOG_SPH) & (Sh::S - 1);
 }
 
-template <int N, int T>
+template <int N, int T, bool F, bool Tl>
 __global__ void __launch_bounds__((soa_shape<N, T>::NT))
     __attribute__((amdgpu_waves_per_eu(soa_shape<N, T>::MIN_WAVES_EU))) k_lanes_soa(SolveArgs a, int factors)
 {
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
     constexpr int KP = (N + T - 1) / T;
     int pv[KP];
     static_for<0, KP>(LUPP_SF(sc) { pv[decltype(sc)::value] = 0; });
-    const int inf = lanes_getrf_solve<N, T>(m, x, pos, g * T, [&](int k, int val) {
+    const int inf = lanes_getrf_solve<N, T, F, Tl>(m, x, pos, g * T, [&](int k, int val) {
         const int c = k / T;
         static_for<0, KP>(LUPP_SF(sc) {
             constexpr int cc = decltype(sc)::value;
@@ -232,8 +232,17 @@ hipError_t launch_lanes_soa(const SolveArgs &a, bool factors, hipStream_t st)
 {
     using Sh = soa_shape<N, T>;
     const int64_t blocks = (a.batch + Sh::S - 1) / Sh::S;
-    hipLaunchKernelGGL((k_lanes_soa<N, T>), dim3((unsigned)blocks), dim3(Sh::NT), 0, st, a,
-                       (int)factors);
+    /* arithmetic x pivoting instances: strict, FMA, strict + tile-local */
+    if (a.fma && a.tile > 0) return hipErrorNotSupported;
+    if (a.fma)
+        hipLaunchKernelGGL((k_lanes_soa<N, T, true, false>), dim3((unsigned)blocks), dim3(Sh::NT), 0,
+                           st, a, (int)factors);
+    else if (a.tile > 0)
+        hipLaunchKernelGGL((k_lanes_soa<N, T, false, true>), dim3((unsigned)blocks), dim3(Sh::NT), 0,
+                           st, a, (int)factors);
+    else
+        hipLaunchKernelGGL((k_lanes_soa<N, T, false, false>), dim3((unsigned)blocks), dim3(Sh::NT),
+                           0, st, a, (int)factors);
     return hipGetLastError();
 }
 

@@ -26,7 +26,7 @@ namespace lupp {
 template <int N>
 constexpr int thread_waves_per_eu() { return N <= 4 ? 4 : (N <= 8 ? 2 : 1); }
 
-template <int N>
+template <int N, bool F, bool Tl>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(thread_waves_per_eu<N>())))
     k_thread(SolveArgs a, int layout, int factors)
@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(256)
         });
     }
 
-    const int inf = thread_getrf_solve<N, true>(m, x, piv, a.tile, a.thresh);
+    const int inf = thread_getrf_solve<N, true, F, Tl>(m, x, piv, a.tile, a.thresh);
 
     bA = opaque_ptr(bA);
     bB = opaque_ptr(bB);
@@ -117,8 +117,17 @@ hipError_t launch_thread(const SolveArgs &a, int layout, bool factors, int wpb, 
 {
     const int threads = 64 * (wpb > 0 ? wpb : 4);
     const int64_t blocks = (a.batch + threads - 1) / threads;
-    hipLaunchKernelGGL((k_thread<N>), dim3((unsigned)blocks), dim3(threads), 0, st, a, layout,
-                       (int)factors);
+    /* arithmetic x pivoting instances: strict, FMA, strict + tile-local */
+    if (a.fma && a.tile > 0) return hipErrorNotSupported;
+    if (a.fma)
+        hipLaunchKernelGGL((k_thread<N, true, false>), dim3((unsigned)blocks), dim3(threads), 0, st,
+                           a, layout, (int)factors);
+    else if (a.tile > 0)
+        hipLaunchKernelGGL((k_thread<N, false, true>), dim3((unsigned)blocks), dim3(threads), 0, st,
+                           a, layout, (int)factors);
+    else
+        hipLaunchKernelGGL((k_thread<N, false, false>), dim3((unsigned)blocks), dim3(threads), 0, st,
+                           a, layout, (int)factors);
     return hipGetLastError();
 }
 
@@ -127,7 +136,7 @@ hipError_t launch_thread(const SolveArgs &a, int layout, bool factors, int wpb, 
 #define LUPP_THREAD_INSTANCE(N)                                                      \
     namespace lupp {                                                                \
     LaunchFn thread_fn_##N() { return launch_thread<N>; }                           \
-    const void *thread_sym_##N() { return reinterpret_cast<const void *>(&k_thread<N>); } \
+    const void *thread_sym_##N() { return reinterpret_cast<const void *>(&k_thread<N, false, false>); } \
     }
 
 #endif

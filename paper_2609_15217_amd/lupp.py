@@ -26,6 +26,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 LUPP_AOS, LUPP_SOA = 0, 1
 LUPP_KEEP_A = 1
+LUPP_FMA = 4
 LUPP_RAGGED_PER_SIZE = 2
 LUPP_VARIANT_AUTO, LUPP_VARIANT_THREAD, LUPP_VARIANT_LANES = 0, 1, 2
 LUPP_LAW_NORTON7, LUPP_LAW_NORTON_AF13 = 7, 13

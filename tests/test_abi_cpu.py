@@ -78,7 +78,7 @@ def test_argument_validation_without_device():
     assert chk(strideB=7) == -9
     assert chk(ipiv=None) == -10
     assert chk(info=None) == -11
-    assert chk(flags=4) == -12
+    assert chk(flags=8) == -12
     # batch 0 accepts null buffers
     assert chk(batch=0, A=None, b=None, ipiv=None, info=None) == 0
     # SoA: the batch stride must cover the batch

@@ -44,7 +44,7 @@ def variants(n):
 
 
 def gpu_solve(L, ctx, A, b, layout, variant=0, lanes=0, wpb=0, keep_a=False, lda=None,
-              stride_pad=0):
+              stride_pad=0, fma=False):
     """Run the library on AoS numpy inputs; return AoS numpy outputs."""
     batch, n = A.shape[0], A.shape[1]
     lda = lda or n
@@ -76,7 +76,7 @@ def gpu_solve(L, ctx, A, b, layout, variant=0, lanes=0, wpb=0, keep_a=False, lda
     assert L.lupp_force_variant(ctx, variant, lanes, wpb) == 0
     try:
         rc = L.lupp_batched_solve(ctx, n, batch, layout, tA, lda, sA, tb, sB, ipiv, info,
-                                  L.LUPP_KEEP_A if keep_a else 0)
+                                  (L.LUPP_KEEP_A if keep_a else 0) | (L.LUPP_FMA if fma else 0))
     finally:
         L.lupp_force_variant(ctx, 0, 0, 0)
     assert rc == 0, L.lupp_error_string(rc)
