@@ -509,23 +509,31 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
         const int tp =
             lanes_pivot_owner<N, T, k, kTile>(a, pos, seg_base, M, lpos, ls, tile, thresh);
         const int src = seg_base + tp;
-        const int ql = bcast_i32((lpos << 8) | ls, src);
-        const int q = ql >> 8;  /* current position of the pivot row */
-        const int sp = ql & 0xff; /* its slot in lane tp */
+        /* Every lane reads its own best candidate slot (ls); the owner's
+         * slot is the pivot row, so broadcasting from the owner needs no
+         * earlier exchange of the slot index: the pivot value and the row go
+         * out right after the reduction, and the pivot's position q (for the
+         * bookkeeping and ipiv) travels beside them, off the critical path. */
         double sel = a[0][k];
         static_for<1, K>(LUPP_SF(sc) {
             constexpr int s = decltype(sc)::value;
-            sel = (sp == s) ? a[s][k] : sel;
+            sel = (ls == s) ? a[s][k] : sel;
         });
         const double pv = bcast_f64(sel, src);
+        const int q = bcast_i32(lpos, src); /* current position of the pivot row */
         ipiv_k(k, q + 1);
 
-        /* positions: the row at position k moves to q, the pivot row takes k */
+        /* trailing rows: every candidate row except the pivot row (the row at
+         * position k, if it is not the pivot, moves to q > k) */
         const bool own = lane_in_seg == tp;
+        bool trail[K];
         static_for<0, K>(LUPP_SF(sc) {
             constexpr int s = decltype(sc)::value;
+            const bool piv = own && ls == s;
+            trail[s] = !piv && pos[s] >= k;
+            /* positions: the row at position k moves to q, the pivot row takes k */
             const int ps = pos[s];
-            pos[s] = (own && sp == s) ? k : ((ps == k) ? q : ps);
+            pos[s] = piv ? k : ((ps == k) ? q : ps);
         });
         const bool zero = (M == 0.0);
         info = (zero && info == 0) ? k + 1 : info;
@@ -535,12 +543,12 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
             static_for<0, K>(LUPP_SF(sc) {
                 constexpr int s = decltype(sc)::value;
                 l[s] = a[s][k] / pv;
-                a[s][k] = pos[s] > k ? l[s] : a[s][k];
+                a[s][k] = trail[s] ? l[s] : a[s][k];
             });
             double ys = b[0];
             static_for<1, K>(LUPP_SF(sc) {
                 constexpr int s = decltype(sc)::value;
-                ys = (sp == s) ? b[s] : ys;
+                ys = (ls == s) ? b[s] : ys;
             });
             const double y = bcast_f64(ys, src);
             static_for<0, (N - k - 1 + CH - 1) / CH>(LUPP_SF(cc) {
@@ -552,13 +560,13 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
                     double us = a[0][j];
                     static_for<1, K>(LUPP_SF(sc) {
                         constexpr int s = decltype(sc)::value;
-                        us = (sp == s) ? a[s][j] : us;
+                        us = (ls == s) ? a[s][j] : us;
                     });
                     u[j - j0] = bcast_f64(us, src);
                 });
                 static_for<0, K>(LUPP_SF(sc) {
                     constexpr int s = decltype(sc)::value;
-                    if (pos[s] > k) {
+                    if (trail[s]) {
                         static_for<j0, j1>(LUPP_SF(jc) {
                             constexpr int j = decltype(jc)::value;
                             a[s][j] = msub<kFMA>(a[s][j], l[s], u[j - j0]);
@@ -570,7 +578,7 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
             if constexpr (k + 1 >= N) {
                 static_for<0, K>(LUPP_SF(sc) {
                     constexpr int s = decltype(sc)::value;
-                    if (pos[s] > k) b[s] = msub<kFMA>(b[s], l[s], y);
+                    if (trail[s]) b[s] = msub<kFMA>(b[s], l[s], y);
                 });
             }
         }
