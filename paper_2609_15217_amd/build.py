@@ -14,6 +14,7 @@ import concurrent.futures as cf
 import hashlib
 import json
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -132,14 +133,34 @@ def generate(gen: str) -> list[str]:
     return srcs
 
 
+_INCLUDE_RE = re.compile(r'^\s*#\s*include\s*"([^"]+)"', re.M)
+
+
+def _local_headers(src: str) -> list[str]:
+    """Headers of this project that `src` includes, directly or not."""
+    seen: dict[str, None] = {}
+    todo = [src]
+    while todo:
+        f = todo.pop()
+        for name in _INCLUDE_RE.findall(open(f, encoding="utf-8", errors="replace").read()):
+            for d in (os.path.dirname(f), CSRC, INCLUDE):
+                p = os.path.join(d, name)
+                if os.path.exists(p):
+                    p = os.path.realpath(p)
+                    if p not in seen:
+                        seen[p] = None
+                        todo.append(p)
+                    break
+    return sorted(seen)
+
+
 def _deps_hash(src: str) -> str:
     h = hashlib.sha256()
     h.update(" ".join(CXXFLAGS).encode())
     h.update(open(src, "rb").read())
-    for d in (CSRC, INCLUDE):
-        for name in sorted(os.listdir(d)):
-            if name.endswith((".h", ".hpp")):
-                h.update(open(os.path.join(d, name), "rb").read())
+    for p in _local_headers(src):
+        h.update(p.encode())
+        h.update(open(p, "rb").read())
     return h.hexdigest()[:20]
 
 

@@ -4,8 +4,9 @@
  * Systems are grouped by size on the device: a histogram, a plan that lays
  * the size bins out in descending n (costliest work first) and cuts each bin
  * into work items, and a scatter of system indices into the bins. The solve
- * is then either one persistent launch whose workgroups pull work items from
- * an atomic counter and dispatch on n, or one launch per size.
+ * is then either two persistent launches (sizes 17..32, then 1..16) whose
+ * workgroups pull work items from an atomic counter and dispatch on n, or one
+ * launch per size.
  *
  * System s: matrix column-major at A + offA[s] (lda = n[s]), right-hand side
  * and pivots at offset offB[s], info[s].
@@ -27,7 +28,9 @@ struct RaggedPlan {
     int32_t cursor[33];     /* scatter cursors */
     int32_t item_start[33]; /* first work item of each size */
     int32_t total_items;
-    int32_t next_item;      /* persistent-launch work counter */
+    int32_t large_items;    /* items of sizes 17..32: numbered 0 .. large_items-1 */
+    int32_t next_item;      /* work counter of the large-size persistent launch */
+    int32_t next_small;     /* work counter of the small-size persistent launch */
     int32_t bad;            /* systems with n outside 1..32 */
 };
 
@@ -42,12 +45,18 @@ struct RaggedArgs {
     RaggedPlan *plan;
 };
 
+/* Sizes above this one are served by the large-size persistent kernel. */
+constexpr int kRaggedSmallMax = 16;
+
 /* Per-size solver used inside the ragged kernels: thread path for n <= 5,
- * T-lane segments above; every choice stays within about 128 VGPRs so the
- * persistent kernel (which holds all sizes) keeps 4 waves per SIMD. */
+ * T-lane segments above. Sizes up to 16 stay within about 128 VGPRs, so the
+ * small-size persistent kernel keeps 4 waves per SIMD; sizes 17..32 use
+ * 16-lane segments (two rows per lane, up to ~200 VGPRs, 2 waves per SIMD),
+ * which solve these sizes faster than 32 lanes of one row each: half the
+ * lanes idle in the pivot search and broadcasts. */
 __host__ __device__ constexpr int ragged_lanes(int n)
 {
-    return n <= 5 ? 1 : (n <= 16 ? 8 : 32);
+    return n <= 5 ? 1 : (n <= kRaggedSmallMax ? 8 : 16);
 }
 
 /* systems one workgroup solves at once for size n */

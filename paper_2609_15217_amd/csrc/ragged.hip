@@ -1,5 +1,5 @@
-/* Ragged (mixed-size) batches: device-side grouping by size and one
- * persistent launch over all sizes (see kernels_ragged.h). */
+/* Ragged (mixed-size) batches: device-side grouping by size and two
+ * persistent launches, one per size class (see kernels_ragged.h). */
 #include <cstring>
 
 #include "kernels_ragged.h"
@@ -44,9 +44,11 @@ __global__ void k_ragged_plan(RaggedPlan *plan)
         const int c = plan->count[n];
         start += c;
         items += (c + ragged_per_item(n) - 1) / ragged_per_item(n);
+        if (n == kRaggedSmallMax + 1) plan->large_items = items;
     }
     plan->total_items = items;
     plan->next_item = 0;
+    plan->next_small = plan->large_items;
 }
 
 /* scatter system indices into their bins: each workgroup reserves one range
@@ -89,40 +91,54 @@ __device__ __forceinline__ bool ragged_try(const RaggedArgs &a, int n, int it)
     return true;
 }
 
-template <int... Ns>
+template <int LO, int... Ns>
 __device__ __forceinline__ void ragged_dispatch(const RaggedArgs &a, int n, int it,
                                                 std::integer_sequence<int, Ns...>)
 {
-    (void)(ragged_try<Ns + 1>(a, n, it) || ...);
+    (void)(ragged_try<LO + Ns>(a, n, it) || ...);
 }
 
-/* Persistent launch: workgroups take work items (largest sizes first) from an
- * atomic counter until every item is taken; every wave leaves the loop on the
- * same broadcast item index. The kernel holds the code of every size; it is
- * held to 4 waves per SIMD (the register budget of the largest single size)
- * at the cost of a few spills outside the solver loops. */
-__global__ void __launch_bounds__(kRaggedThreads) __attribute__((amdgpu_waves_per_eu(4)))
-    k_ragged_persistent(RaggedArgs a)
+/* Persistent loop over the work items [first, end) of sizes LO..HI:
+ * workgroups take items (largest sizes first) from the atomic `counter`
+ * until every item is taken; every wave leaves the loop on the same
+ * broadcast item index. */
+template <int LO, int HI>
+__device__ __forceinline__ void ragged_persistent_loop(const RaggedArgs &a, int32_t *counter, int end)
 {
     __shared__ int sh_item;
     const RaggedPlan *plan = a.plan;
-    const int total = plan->total_items;
     for (;;) {
-        if (threadIdx.x == 0) sh_item = atomicAdd(&a.plan->next_item, 1);
+        if (threadIdx.x == 0) sh_item = atomicAdd(counter, 1);
         __syncthreads();
         const int it = __builtin_amdgcn_readfirstlane(sh_item);
         __syncthreads();
-        if (it >= total) break;
-        int n = 1;
-        for (int m = 1; m <= 32; ++m) {
+        if (it >= end) break;
+        int n = LO;
+        for (int m = LO; m <= HI; ++m) {
             const int c = plan->count[m];
             const int nitems = (c + ragged_per_item(m) - 1) / ragged_per_item(m);
             const int st = plan->item_start[m];
             if (it >= st && it < st + nitems) n = m;
         }
         n = __builtin_amdgcn_readfirstlane(n);
-        ragged_dispatch(a, n, it, std::make_integer_sequence<int, 32>{});
+        ragged_dispatch<LO>(a, n, it, std::make_integer_sequence<int, HI - LO + 1>{});
     }
+}
+
+/* Sizes 17..32 (items 0 .. large_items-1): 16-lane segments need up to ~200
+ * VGPRs, so this kernel runs 2 waves per SIMD. */
+__global__ void __launch_bounds__(kRaggedThreads) __attribute__((amdgpu_waves_per_eu(2)))
+    k_ragged_large(RaggedArgs a)
+{
+    ragged_persistent_loop<kRaggedSmallMax + 1, 32>(a, &a.plan->next_item, a.plan->large_items);
+}
+
+/* Sizes 1..16 (items large_items .. total_items-1), held to 4 waves per SIMD
+ * (the register budget of its largest size). */
+__global__ void __launch_bounds__(kRaggedThreads) __attribute__((amdgpu_waves_per_eu(4)))
+    k_ragged_small(RaggedArgs a)
+{
+    ragged_persistent_loop<1, kRaggedSmallMax>(a, &a.plan->next_small, a.plan->total_items);
 }
 
 hipError_t ragged_one_launch(int n, const RaggedArgs &a, int items, hipStream_t st);
@@ -177,8 +193,10 @@ int ragged_launch_impl(RaggedWs *ws, int64_t batch, const int32_t *n, const int6
         int dev = 0, cus = 256;
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        hipLaunchKernelGGL(k_ragged_persistent, dim3((unsigned)(cus * 4)), dim3(kRaggedThreads), 0,
-                           st, a);
+        /* as many workgroups as stay resident: a CU holds 4 SIMDs x (waves per
+         * SIMD) waves, 4 waves per workgroup */
+        hipLaunchKernelGGL(k_ragged_large, dim3((unsigned)(cus * 2)), dim3(kRaggedThreads), 0, st, a);
+        hipLaunchKernelGGL(k_ragged_small, dim3((unsigned)(cus * 4)), dim3(kRaggedThreads), 0, st, a);
         return hip_err(hipGetLastError());
     }
     /* one launch per size: the host reads the plan (a synchronisation) */
