@@ -438,6 +438,7 @@ def main():
         ragged["workload"] = ("2,000,000 FP64 systems, n ~ U{2..32}, A ~ N(0,1) rejected if "
                               "cond2 > 1e4, AoS packed with int64 offsets, seed 3")
         ragged["algorithmic_bytes"] = alg_bytes
+        ragged["lanes_per_size"] = {n: L.lupp_get_ragged_lanes(ctx, n) for n in range(1, 33)}
         ragged["speedup_persistent_vs_per_size"] = round(
             ragged["per_size"]["ms"] / ragged["persistent"]["ms"], 3)
         del tn, toA, toB, pA, pb, wA, wb, rip, rin, mx

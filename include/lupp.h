@@ -119,13 +119,41 @@ int lupp_check_solve_args(int n, int64_t batch, int layout, const double *A, int
  * Systems must not overlap. n, offA, offB are device arrays of `batch`
  * (<= 2^31 - 1) entries. The library groups systems by size on the device
  * (histogram, plan, scatter; workspace owned by the context, grown with
- * hipMalloc when a larger batch arrives) and serves every size from one
- * persistent kernel launch, largest sizes first. A system whose n is outside
- * 1..32 gets info = -1 and is not touched. flags: LUPP_KEEP_A,
+ * hipMalloc when a larger batch arrives) and serves the sizes from two
+ * persistent kernel launches queued back to back on `stream` (sizes 17..32,
+ * then 1..16: each kernel's register budget fits its sizes), largest sizes
+ * first; no host synchronisation. Each size uses the lane count of the
+ * context's ragged table (lupp_set_ragged_lanes). A system whose n is
+ * outside 1..32 gets info = -1 and is not touched. flags: LUPP_KEEP_A,
  * LUPP_RAGGED_PER_SIZE. */
 int lupp_batched_solve_ragged(lupp_ctx *ctx, int64_t batch, const int32_t *n,
                               const int64_t *offA, const int64_t *offB, double *A, double *b,
                               int32_t *ipiv, int32_t *info, unsigned flags, void *stream);
+
+/* Lanes per system of the ragged path (Section 4.1: size-aware dispatch).
+ * The ragged kernels hold, for every size n, the lane counts
+ * lupp_ragged_lanes_supported(n, lanes) accepts: 1 (one thread per system,
+ * n <= 5), 2 (n = 2..4), 4 (n = 3..8), 8 (n = 5..16) and 16 (n >= 9).
+ * 32 lanes (measured slower than 16 for every n >= 17) and 64 (half of a
+ * wave64 without a row for any n <= 32) are not built. A context starts from the table the autotuner
+ * measured on gfx950. lupp_ragged_lanes_supported: 1 or 0 (host-only, no
+ * device needed). lupp_set_ragged_lanes: 0, -2 for n outside 1..32, -3 for
+ * an unsupported lane count. lupp_get_ragged_lanes: the lane count, or -2. */
+int lupp_ragged_lanes_supported(int n, int lanes);
+int lupp_set_ragged_lanes(lupp_ctx *ctx, int n, int lanes);
+int lupp_get_ragged_lanes(const lupp_ctx *ctx, int n);
+
+/* Autotune the ragged lane count of size n: time the persistent ragged path
+ * (the same call lupp_batched_solve_ragged makes) on `batch` systems of size
+ * n for every supported lane count, keep the fastest in the context's ragged
+ * table and report it (lanes, median ms). A is `batch` packed column-major
+ * n x n matrices (device, read only), b `batch` packed right-hand sides.
+ * Synchronous: allocates and frees its own device workspace (copies of A and
+ * b, offsets, pivots, info) and waits for `stream`. reps >= 1 timed runs per
+ * candidate after one warm-up. Returns 0, -2 (n), -3 (batch outside
+ * 1..2^31-1), -4 / -5 (NULL A / b), -6 (reps), or an error code. */
+int lupp_autotune_ragged(lupp_ctx *ctx, int n, int64_t batch, const double *A, const double *b,
+                         int reps, int *lanes, float *ms, void *stream);
 
 /* Pivoting rule of later lupp_batched_solve calls on this context.
  *   tile = 0 (the default): textbook partial pivoting (Section 2.2).

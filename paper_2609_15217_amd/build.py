@@ -123,6 +123,15 @@ def generate(gen: str) -> list[str]:
         lines.append(f"  if (n == {n} && layout == {lay} && bucket == {bk}) {{ *v = {v}; *l = {int(e['lanes'])}; "
                      f"*w = {int(e['wpb'])}; return true; }}")
     lines.append("  (void)n; (void)layout; (void)bucket; (void)v; (void)l; (void)w;\n  return false;\n}")
+    # lanes per size of the ragged path, measured by lupp_autotune_ragged
+    ragged = {}
+    if os.path.exists(tp):
+        for e in json.load(open(tp)).get("ragged", []):
+            ragged[int(e["n"])] = int(e["lanes"])
+    lines.append("bool tuned_ragged(int n, int *lanes) {")
+    for n, t in sorted(ragged.items()):
+        lines.append(f"  if (n == {n}) {{ *lanes = {t}; return true; }}")
+    lines.append("  (void)n; (void)lanes;\n  return false;\n}")
     lines.append("}  // namespace lupp")
     p = os.path.join(gen, "registry.hip")
     _write_if_changed(p, "\n".join(lines) + "\n")
@@ -223,6 +232,8 @@ def _weight(src: str) -> int:
     if b.startswith("thread_"):
         n = int(b[7:-4])
         return 4 * n ** 3
+    if b in ("ragged_large.hip", "ragged_small.hip"):
+        return 400_000
     if b.startswith("ragged"):
         return 200_000
     return 50_000 if "constitutive" in b else 0

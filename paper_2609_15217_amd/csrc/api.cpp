@@ -29,6 +29,7 @@ struct lupp_ctx {
                            lupp::newton_default_lanes(LUPP_LAW_NORTON_AF13)};
     int tile = 0;          /* pivoting of lupp_batched_solve: 0 textbook, else tile-local */
     double thresh = 0.0;
+    uint8_t ragged_lanes[33] = {}; /* lanes per system of the ragged path, per size */
 };
 
 namespace lupp {
@@ -89,6 +90,11 @@ int lupp_create(lupp_ctx **ctx, int device)
     for (int n = 0; n <= 32; ++n)
         for (int l = 0; l < 2; ++l)
             for (int bk = 0; bk < 2; ++bk) c->table[n][l][bk] = default_choice(n < 1 ? 1 : n, l, bk);
+    for (int n = 1; n <= 32; ++n) {
+        int t = 0;
+        c->ragged_lanes[n] = (uint8_t)((tuned_ragged(n, &t) && ragged_lanes_ok(n, t))
+                                           ? t : ragged_default_lanes(n));
+    }
     *ctx = c;
     return 0;
 }
@@ -226,9 +232,46 @@ int lupp_batched_solve_ragged(lupp_ctx *ctx, int64_t batch, const int32_t *n,
     hipGetDevice(&cur);
     if (cur != ctx->device) hipSetDevice(ctx->device);
     if (ctx->ragged_ws == nullptr) ctx->ragged_ws = ragged_ws_create();
-    const int rc = ragged_launch_impl(ctx->ragged_ws, batch, n, offA, offB, A, b, ipiv, info,
-                                      (flags & LUPP_KEEP_A) == 0,
+    const int rc = ragged_launch_impl(ctx->ragged_ws, ctx->ragged_lanes, batch, n, offA, offB, A,
+                                      b, ipiv, info, (flags & LUPP_KEEP_A) == 0,
                                       (flags & LUPP_RAGGED_PER_SIZE) != 0, (hipStream_t)stream);
+    if (cur != ctx->device) hipSetDevice(cur);
+    return rc;
+}
+
+int lupp_ragged_lanes_supported(int n, int lanes) { return ragged_lanes_ok(n, lanes) ? 1 : 0; }
+
+int lupp_set_ragged_lanes(lupp_ctx *ctx, int n, int lanes)
+{
+    if (ctx == nullptr) return -1;
+    if (n < 1 || n > 32) return -2;
+    if (!ragged_lanes_ok(n, lanes)) return -3;
+    ctx->ragged_lanes[n] = (uint8_t)lanes;
+    return 0;
+}
+
+int lupp_get_ragged_lanes(const lupp_ctx *ctx, int n)
+{
+    if (ctx == nullptr) return -1;
+    if (n < 1 || n > 32) return -2;
+    return ctx->ragged_lanes[n];
+}
+
+int lupp_autotune_ragged(lupp_ctx *ctx, int n, int64_t batch, const double *A, const double *b,
+                         int reps, int *lanes, float *ms, void *stream)
+{
+    if (ctx == nullptr) return -1;
+    if (n < 1 || n > 32) return -2;
+    if (batch < 1 || batch > 0x7fffffff) return -3;
+    if (A == nullptr) return -4;
+    if (b == nullptr) return -5;
+    if (reps < 1) return -6;
+    int cur = 0;
+    hipGetDevice(&cur);
+    if (cur != ctx->device) hipSetDevice(ctx->device);
+    if (ctx->ragged_ws == nullptr) ctx->ragged_ws = ragged_ws_create();
+    const int rc = ragged_autotune_impl(ctx->ragged_ws, ctx->ragged_lanes, n, batch, A, b, reps,
+                                        lanes, ms, (hipStream_t)stream);
     if (cur != ctx->device) hipSetDevice(cur);
     return rc;
 }

@@ -65,9 +65,44 @@ const void *constitutive_kernel_symbol(int kind, bool tangent);
 struct RaggedWs;
 RaggedWs *ragged_ws_create();
 void ragged_ws_destroy(RaggedWs *ws);
-int ragged_launch_impl(RaggedWs *ws, int64_t batch, const int32_t *n, const int64_t *offA,
-                       const int64_t *offB, double *A, double *b, int32_t *ipiv, int32_t *info,
-                       bool factors, bool per_size, hipStream_t stream);
+/* lanes[n] (n = 1..32): lanes per system used for size n (ragged_lanes_ok). */
+int ragged_launch_impl(RaggedWs *ws, const uint8_t *lanes, int64_t batch, const int32_t *n,
+                       const int64_t *offA, const int64_t *offB, double *A, double *b,
+                       int32_t *ipiv, int32_t *info, bool factors, bool per_size,
+                       hipStream_t stream);
+/* Time the persistent ragged path on a batch of `batch` systems of size n
+ * (AoS, packed) for every lane count compiled for n; lanes[n] is left at the
+ * fastest (median of reps timed runs after one warm-up). */
+int ragged_autotune_impl(RaggedWs *ws, uint8_t *lanes, int n, int64_t batch, const double *A,
+                         const double *b, int reps, int *best, float *best_ms, hipStream_t st);
+/* Measured default lanes per size for the ragged path (compiled in from
+ * the autotuner's table); false if the table has no entry for n. */
+bool tuned_ragged(int n, int *lanes);
+
+/* Sizes above this one are served by the large-size ragged kernel. */
+constexpr int kRaggedSmallMax = 16;
+
+/* Lane counts compiled into the ragged kernels for size n. Sizes up to 16
+ * share one kernel held to 128 VGPRs (4 waves per SIMD): the thread path up
+ * to n = 5 and segments of 2, 4, 8 or 16 lanes where the rows fit; sizes
+ * 17..32 run in a kernel with up to 256 VGPRs (2 waves per SIMD) with 16
+ * lanes, two rows each (one row on each of 32 lanes measured slower at every
+ * one of these sizes, standalone and in the ragged kernel, so it is not
+ * compiled in: it would double the kernel's code). */
+__host__ __device__ constexpr bool ragged_lanes_ok(int n, int T)
+{
+    if (n < 1 || n > 32) return false;
+    if (n > kRaggedSmallMax) return T == 16;
+    return (T == 1 && n <= 5) || (T == 2 && n >= 2 && n <= 4) || (T == 4 && n >= 3 && n <= 8) ||
+           (T == 8 && n >= 5) || (T == 16 && n >= 9);
+}
+
+/* Lanes per size before any measurement: the thread path while the system
+ * is tiny, 8-lane segments up to 16, 16-lane segments above. */
+__host__ __device__ constexpr int ragged_default_lanes(int n)
+{
+    return n <= 5 ? 1 : (n <= kRaggedSmallMax ? 8 : 16);
+}
 
 /* ------------------------------------------------------------------------ */
 /* Device-side memory access through buffer resources.                      */

@@ -14,6 +14,8 @@
 #ifndef LUPP_KERNELS_RAGGED_H
 #define LUPP_KERNELS_RAGGED_H
 
+#include <utility>
+
 #include "internal.h"
 #include "lupp_device.h"
 
@@ -43,26 +45,13 @@ struct RaggedArgs {
     int factors;
     int32_t *sorted;
     RaggedPlan *plan;
+    uint8_t lanes[33]; /* lanes per system for each size (ragged_lanes_ok) */
 };
 
-/* Sizes above this one are served by the large-size persistent kernel. */
-constexpr int kRaggedSmallMax = 16;
-
-/* Per-size solver used inside the ragged kernels: thread path for n <= 5,
- * T-lane segments above. Sizes up to 16 stay within about 128 VGPRs, so the
- * small-size persistent kernel keeps 4 waves per SIMD; sizes 17..32 use
- * 16-lane segments (two rows per lane, up to ~200 VGPRs, 2 waves per SIMD),
- * which solve these sizes faster than 32 lanes of one row each: half the
- * lanes idle in the pivot search and broadcasts. */
-__host__ __device__ constexpr int ragged_lanes(int n)
+/* systems one workgroup solves at once with T lanes per system */
+__host__ __device__ constexpr int ragged_per_round(int T)
 {
-    return n <= 5 ? 1 : (n <= kRaggedSmallMax ? 8 : 16);
-}
-
-/* systems one workgroup solves at once for size n */
-__host__ __device__ constexpr int ragged_per_round(int n)
-{
-    return ragged_lanes(n) == 1 ? kRaggedThreads : kRaggedWaves * (64 / ragged_lanes(n));
+    return T == 1 ? kRaggedThreads : kRaggedWaves * (64 / T);
 }
 
 /* rounds per work item: items large enough to amortise taking one from the
@@ -70,15 +59,14 @@ __host__ __device__ constexpr int ragged_per_round(int n)
 constexpr int kRaggedRounds = 4;
 
 /* systems handled by one workgroup for one work item */
-__host__ __device__ constexpr int ragged_per_item(int n)
+__host__ __device__ constexpr int ragged_per_item(int T)
 {
-    return kRaggedRounds * ragged_per_round(n);
+    return kRaggedRounds * ragged_per_round(T);
 }
 
-template <int N>
+template <int N, int T>
 __device__ __forceinline__ void ragged_item(const RaggedArgs &a, int first, int cnt)
 {
-    constexpr int T = ragged_lanes(N);
     const int32_t *idx = a.sorted + a.plan->bin_start[N] + first;
     if constexpr (T == 1) {
         const int i = threadIdx.x;
@@ -176,18 +164,39 @@ __device__ __forceinline__ void ragged_item(const RaggedArgs &a, int first, int 
     }
 }
 
-/* Solve the work item `it` of size N (all threads of the workgroup). */
+template <int N, int T>
+__device__ __forceinline__ void ragged_run_item_t(const RaggedArgs &a, int it)
+{
+    const int first = (it - a.plan->item_start[N]) * ragged_per_item(T);
+    for (int r = 0; r < kRaggedRounds; ++r) {
+        const int f = first + r * ragged_per_round(T);
+        const int rest = a.plan->count[N] - f;
+        if (rest <= 0) break;
+        ragged_item<N, T>(a, f, rest < ragged_per_round(T) ? rest : ragged_per_round(T));
+    }
+}
+
+template <int N, int T>
+__device__ __forceinline__ bool ragged_try_lanes(const RaggedArgs &a, int lanes, int it)
+{
+    if constexpr (ragged_lanes_ok(N, T)) {
+        if (lanes == T) {
+            ragged_run_item_t<N, T>(a, it);
+            return true;
+        }
+    }
+    return false;
+}
+
+/* Solve the work item `it` of size N (all threads of the workgroup) with the
+ * lane count the table gives for N (uniform across the workgroup). */
 template <int N>
 __device__ __forceinline__ void ragged_run_item(const RaggedArgs &a, int it)
 {
-    const int local = it - a.plan->item_start[N];
-    const int first = local * ragged_per_item(N);
-    for (int r = 0; r < kRaggedRounds; ++r) {
-        const int f = first + r * ragged_per_round(N);
-        const int rest = a.plan->count[N] - f;
-        if (rest <= 0) break;
-        ragged_item<N>(a, f, rest < ragged_per_round(N) ? rest : ragged_per_round(N));
-    }
+    const int lanes = __builtin_amdgcn_readfirstlane((int)a.lanes[N]);
+    (void)(ragged_try_lanes<N, 1>(a, lanes, it) || ragged_try_lanes<N, 2>(a, lanes, it) ||
+           ragged_try_lanes<N, 4>(a, lanes, it) || ragged_try_lanes<N, 8>(a, lanes, it) ||
+           ragged_try_lanes<N, 16>(a, lanes, it) || ragged_try_lanes<N, 32>(a, lanes, it));
 }
 
 /* One size per launch: workgroup b solves work item b of size N. */
@@ -197,6 +206,54 @@ __global__ void __launch_bounds__(kRaggedThreads) k_ragged_one(RaggedArgs a)
     const int it = a.plan->item_start[N] + (int)blockIdx.x;
     ragged_run_item<N>(a, it);
 }
+
+template <int N>
+__device__ __forceinline__ bool ragged_try(const RaggedArgs &a, int n, int it)
+{
+    if (n != N) return false;
+    ragged_run_item<N>(a, it);
+    return true;
+}
+
+template <int LO, int... Ns>
+__device__ __forceinline__ void ragged_dispatch(const RaggedArgs &a, int n, int it,
+                                                std::integer_sequence<int, Ns...>)
+{
+    (void)(ragged_try<LO + Ns>(a, n, it) || ...);
+}
+
+/* Persistent loop over the work items [first, end) of sizes LO..HI:
+ * workgroups take items (largest sizes first) from the atomic `counter`
+ * until every item is taken; every wave leaves the loop on the same
+ * broadcast item index. */
+template <int LO, int HI>
+__device__ __forceinline__ void ragged_persistent_loop(const RaggedArgs &a, int32_t *counter, int end)
+{
+    __shared__ int sh_item;
+    const RaggedPlan *plan = a.plan;
+    for (;;) {
+        if (threadIdx.x == 0) sh_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(sh_item);
+        __syncthreads();
+        if (it >= end) break;
+        int n = LO;
+        for (int m = LO; m <= HI; ++m) {
+            const int c = plan->count[m];
+            const int per = ragged_per_item(a.lanes[m]);
+            const int nitems = (c + per - 1) / per;
+            const int st = plan->item_start[m];
+            if (it >= st && it < st + nitems) n = m;
+        }
+        n = __builtin_amdgcn_readfirstlane(n);
+        ragged_dispatch<LO>(a, n, it, std::make_integer_sequence<int, HI - LO + 1>{});
+    }
+}
+
+/* The two persistent kernels (ragged_large.hip, ragged_small.hip: separate
+ * translation units, compiled in parallel): `grid` workgroups each. */
+hipError_t ragged_large_launch(const RaggedArgs &a, unsigned grid, hipStream_t st);
+hipError_t ragged_small_launch(const RaggedArgs &a, unsigned grid, hipStream_t st);
 
 }  // namespace lupp
 

@@ -32,18 +32,21 @@ __global__ void __launch_bounds__(256) k_ragged_hist(RaggedArgs a)
     if (threadIdx.x == 0 && h[0] != 0) atomicAdd(&a.plan->bad, h[0]);
 }
 
-/* bins in descending size, work items per bin */
-__global__ void k_ragged_plan(RaggedPlan *plan)
+/* bins in descending size, work items per bin (their size follows the lane
+ * count of the size) */
+__global__ void k_ragged_plan(RaggedArgs a)
 {
     if (threadIdx.x != 0) return;
+    RaggedPlan *plan = a.plan;
     int start = 0, items = 0;
     for (int n = 32; n >= 1; --n) {
         plan->bin_start[n] = start;
         plan->item_start[n] = items;
         plan->cursor[n] = 0;
         const int c = plan->count[n];
+        const int per = ragged_per_item(a.lanes[n]);
         start += c;
-        items += (c + ragged_per_item(n) - 1) / ragged_per_item(n);
+        items += (c + per - 1) / per;
         if (n == kRaggedSmallMax + 1) plan->large_items = items;
     }
     plan->total_items = items;
@@ -83,64 +86,6 @@ __global__ void __launch_bounds__(256) k_ragged_scatter(RaggedArgs a)
     }
 }
 
-template <int N>
-__device__ __forceinline__ bool ragged_try(const RaggedArgs &a, int n, int it)
-{
-    if (n != N) return false;
-    ragged_run_item<N>(a, it);
-    return true;
-}
-
-template <int LO, int... Ns>
-__device__ __forceinline__ void ragged_dispatch(const RaggedArgs &a, int n, int it,
-                                                std::integer_sequence<int, Ns...>)
-{
-    (void)(ragged_try<LO + Ns>(a, n, it) || ...);
-}
-
-/* Persistent loop over the work items [first, end) of sizes LO..HI:
- * workgroups take items (largest sizes first) from the atomic `counter`
- * until every item is taken; every wave leaves the loop on the same
- * broadcast item index. */
-template <int LO, int HI>
-__device__ __forceinline__ void ragged_persistent_loop(const RaggedArgs &a, int32_t *counter, int end)
-{
-    __shared__ int sh_item;
-    const RaggedPlan *plan = a.plan;
-    for (;;) {
-        if (threadIdx.x == 0) sh_item = atomicAdd(counter, 1);
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(sh_item);
-        __syncthreads();
-        if (it >= end) break;
-        int n = LO;
-        for (int m = LO; m <= HI; ++m) {
-            const int c = plan->count[m];
-            const int nitems = (c + ragged_per_item(m) - 1) / ragged_per_item(m);
-            const int st = plan->item_start[m];
-            if (it >= st && it < st + nitems) n = m;
-        }
-        n = __builtin_amdgcn_readfirstlane(n);
-        ragged_dispatch<LO>(a, n, it, std::make_integer_sequence<int, HI - LO + 1>{});
-    }
-}
-
-/* Sizes 17..32 (items 0 .. large_items-1): 16-lane segments need up to ~200
- * VGPRs, so this kernel runs 2 waves per SIMD. */
-__global__ void __launch_bounds__(kRaggedThreads) __attribute__((amdgpu_waves_per_eu(2)))
-    k_ragged_large(RaggedArgs a)
-{
-    ragged_persistent_loop<kRaggedSmallMax + 1, 32>(a, &a.plan->next_item, a.plan->large_items);
-}
-
-/* Sizes 1..16 (items large_items .. total_items-1), held to 4 waves per SIMD
- * (the register budget of its largest size). */
-__global__ void __launch_bounds__(kRaggedThreads) __attribute__((amdgpu_waves_per_eu(4)))
-    k_ragged_small(RaggedArgs a)
-{
-    ragged_persistent_loop<1, kRaggedSmallMax>(a, &a.plan->next_small, a.plan->total_items);
-}
-
 hipError_t ragged_one_launch(int n, const RaggedArgs &a, int items, hipStream_t st);
 
 struct RaggedWs {
@@ -159,9 +104,9 @@ void ragged_ws_destroy(RaggedWs *ws)
     delete ws;
 }
 
-int ragged_launch_impl(RaggedWs *ws, int64_t batch, const int32_t *n, const int64_t *offA,
-                       const int64_t *offB, double *A, double *b, int32_t *ipiv, int32_t *info,
-                       bool factors, bool per_size, hipStream_t st)
+int ragged_launch_impl(RaggedWs *ws, const uint8_t *lanes, int64_t batch, const int32_t *n,
+                       const int64_t *offA, const int64_t *offB, double *A, double *b,
+                       int32_t *ipiv, int32_t *info, bool factors, bool per_size, hipStream_t st)
 {
     if (batch > 0x7fffffff) return LUPP_E_UNSUPPORTED;
     if (ws->cap < batch) {
@@ -181,11 +126,12 @@ int ragged_launch_impl(RaggedWs *ws, int64_t batch, const int32_t *n, const int6
         hipError_t e = hipMalloc(&ws->plan, sizeof(RaggedPlan));
         if (e != hipSuccess) return hip_err(e);
     }
-    RaggedArgs a{batch, n, offA, offB, A, b, ipiv, info, factors ? 1 : 0, ws->sorted, ws->plan};
+    RaggedArgs a{batch, n, offA, offB, A, b, ipiv, info, factors ? 1 : 0, ws->sorted, ws->plan, {}};
+    for (int m = 0; m <= 32; ++m) a.lanes[m] = m >= 1 ? lanes[m] : 1;
     const unsigned blocks = (unsigned)((batch + 255) / 256);
     hipLaunchKernelGGL(k_ragged_zero, dim3(1), dim3(64), 0, st, ws->plan);
     hipLaunchKernelGGL(k_ragged_hist, dim3(blocks), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_ragged_plan, dim3(1), dim3(64), 0, st, ws->plan);
+    hipLaunchKernelGGL(k_ragged_plan, dim3(1), dim3(64), 0, st, a);
     hipLaunchKernelGGL(k_ragged_scatter, dim3(blocks), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_err(e);
@@ -195,9 +141,9 @@ int ragged_launch_impl(RaggedWs *ws, int64_t batch, const int32_t *n, const int6
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         /* as many workgroups as stay resident: a CU holds 4 SIMDs x (waves per
          * SIMD) waves, 4 waves per workgroup */
-        hipLaunchKernelGGL(k_ragged_large, dim3((unsigned)(cus * 2)), dim3(kRaggedThreads), 0, st, a);
-        hipLaunchKernelGGL(k_ragged_small, dim3((unsigned)(cus * 4)), dim3(kRaggedThreads), 0, st, a);
-        return hip_err(hipGetLastError());
+        e = ragged_large_launch(a, (unsigned)(cus * 2), st);
+        if (e == hipSuccess) e = ragged_small_launch(a, (unsigned)(cus * 4), st);
+        return hip_err(e);
     }
     /* one launch per size: the host reads the plan (a synchronisation) */
     RaggedPlan h;
@@ -205,11 +151,95 @@ int ragged_launch_impl(RaggedWs *ws, int64_t batch, const int32_t *n, const int6
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_err(e);
     for (int m = 32; m >= 1; --m) {
-        const int items = (h.count[m] + ragged_per_item(m) - 1) / ragged_per_item(m);
+        const int per = ragged_per_item(a.lanes[m]);
+        const int items = (h.count[m] + per - 1) / per;
         e = ragged_one_launch(m, a, items, st);
         if (e != hipSuccess) return hip_err(e);
     }
     return 0;
+}
+
+/* offsets of a packed single-size batch: system s at s*n*n (matrix) and s*n
+ * (right-hand side, pivots) */
+__global__ void __launch_bounds__(256) k_ragged_uniform(int64_t batch, int n, int32_t *nv,
+                                                        int64_t *offA, int64_t *offB)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= batch) return;
+    nv[s] = n;
+    offA[s] = s * n * n;
+    offB[s] = s * n;
+}
+
+int ragged_autotune_impl(RaggedWs *ws, uint8_t *lanes, int n, int64_t batch, const double *A,
+                         const double *b, int reps, int *best, float *best_ms, hipStream_t st)
+{
+    const size_t nA = (size_t)batch * n * n, nB = (size_t)batch * n;
+    double *wA = nullptr, *wB = nullptr;
+    int32_t *wN = nullptr, *wP = nullptr, *wI = nullptr;
+    int64_t *oA = nullptr, *oB = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = 0;
+    hipError_t e = hipMalloc(&wA, nA * 8);
+    if (e == hipSuccess) e = hipMalloc(&wB, nB * 8);
+    if (e == hipSuccess) e = hipMalloc(&wN, (size_t)batch * 4);
+    if (e == hipSuccess) e = hipMalloc(&wP, nB * 4);
+    if (e == hipSuccess) e = hipMalloc(&wI, (size_t)batch * 4);
+    if (e == hipSuccess) e = hipMalloc(&oA, (size_t)batch * 8);
+    if (e == hipSuccess) e = hipMalloc(&oB, (size_t)batch * 8);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? LUPP_E_NOMEM : hip_err(e);
+    if (rc == 0) {
+        hipLaunchKernelGGL(k_ragged_uniform, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, st,
+                           batch, n, wN, oA, oB);
+        e = hipGetLastError();
+        if (e != hipSuccess) rc = hip_err(e);
+    }
+    const uint8_t keep = lanes[n];
+    int pick = 0;
+    float pick_ms = 3.0e38f;
+    const int cands[6] = {1, 2, 4, 8, 16, 32};
+    for (int c = 0; c < 6 && rc == 0; ++c) {
+        if (!ragged_lanes_ok(n, cands[c])) continue;
+        lanes[n] = (uint8_t)cands[c];
+        float t[64];
+        const int r_total = reps + 1 < 64 ? reps + 1 : 64;
+        for (int r = 0; r < r_total && rc == 0; ++r) {
+            e = hipMemcpyAsync(wA, A, nA * 8, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(wB, b, nB * 8, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            if (e != hipSuccess) { rc = hip_err(e); break; }
+            rc = ragged_launch_impl(ws, lanes, batch, wN, oA, oB, wA, wB, wP, wI, true, false, st);
+            if (rc != 0) break;
+            e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t[r], e0, e1);
+            if (e != hipSuccess) rc = hip_err(e);
+        }
+        if (rc != 0) break;
+        /* median of the timed repetitions (the first run is a warm-up) */
+        for (int i = 1; i < r_total; ++i)
+            for (int j = i + 1; j < r_total; ++j)
+                if (t[j] < t[i]) { const float x = t[i]; t[i] = t[j]; t[j] = x; }
+        const float med = t[1 + (r_total - 1) / 2];
+        if (med < pick_ms) { pick_ms = med; pick = cands[c]; }
+    }
+    lanes[n] = (rc == 0 && pick != 0) ? (uint8_t)pick : keep;
+    if (rc == 0) {
+        if (best) *best = pick;
+        if (best_ms) *best_ms = pick_ms;
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(wA);
+    hipFree(wB);
+    hipFree(wN);
+    hipFree(wP);
+    hipFree(wI);
+    hipFree(oA);
+    hipFree(oB);
+    return rc;
 }
 
 }  // namespace lupp

@@ -86,6 +86,13 @@ _lupp_autotune = _sig("lupp_autotune", ctypes.c_int,
                       [_P, ctypes.c_int, _i64, ctypes.c_int, _P, _i64, _i64, _P, _i64, ctypes.c_int,
                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float), _P])
+_lupp_ragged_lanes_supported = _sig("lupp_ragged_lanes_supported", ctypes.c_int,
+                                    [ctypes.c_int, ctypes.c_int])
+_lupp_set_ragged_lanes = _sig("lupp_set_ragged_lanes", ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int])
+_lupp_get_ragged_lanes = _sig("lupp_get_ragged_lanes", ctypes.c_int, [_P, ctypes.c_int])
+_lupp_autotune_ragged = _sig("lupp_autotune_ragged", ctypes.c_int,
+                             [_P, ctypes.c_int, _i64, _P, _P, ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float), _P])
 _lupp_check_solve_args = _sig("lupp_check_solve_args", ctypes.c_int,
                               [ctypes.c_int, _i64, ctypes.c_int, _P, _i64, _i64, _P, _i64, _P, _P,
                                ctypes.c_uint])
@@ -132,7 +139,9 @@ EXPORTED = ["lupp_create", "lupp_destroy", "lupp_batched_solve", "lupp_batched_s
             "lupp_server_poll", "lupp_server_wait", "lupp_server_get_stats",
             "lupp_server_reset_stats", "lupp_sweep_create", "lupp_sweep_launch",
             "lupp_sweep_destroy", "constitutive_update_batched", "lupp_set_newton_variant",
-            "lupp_get_newton_variant", "lupp_set_pivoting", "lupp_get_pivoting"]
+            "lupp_get_newton_variant", "lupp_set_pivoting", "lupp_get_pivoting",
+            "lupp_ragged_lanes_supported", "lupp_set_ragged_lanes", "lupp_get_ragged_lanes",
+            "lupp_autotune_ragged"]
 
 
 class LuppError(RuntimeError):
@@ -228,6 +237,26 @@ def lupp_autotune(ctx: Context, n: int, batch: int, layout: int, A, lda: int, st
                         ctypes.byref(v), ctypes.byref(l), ctypes.byref(w), ctypes.byref(ms),
                         _stream(stream))
     return rc, v.value, l.value, w.value, ms.value
+
+
+def lupp_ragged_lanes_supported(n: int, lanes: int) -> int:
+    return _lupp_ragged_lanes_supported(n, lanes)
+
+
+def lupp_set_ragged_lanes(ctx: Context, n: int, lanes: int) -> int:
+    return _lupp_set_ragged_lanes(ctx.handle, n, lanes)
+
+
+def lupp_get_ragged_lanes(ctx: Context, n: int) -> int:
+    return _lupp_get_ragged_lanes(ctx.handle, n)
+
+
+def lupp_autotune_ragged(ctx: Context, n: int, batch: int, A, b, reps: int = 5, stream=None):
+    """Returns (rc, lanes, ms)."""
+    l, ms = ctypes.c_int(), ctypes.c_float()
+    rc = _lupp_autotune_ragged(ctx.handle, n, batch, _ptr(A), _ptr(b), reps, ctypes.byref(l),
+                               ctypes.byref(ms), _stream(stream))
+    return rc, l.value, ms.value
 
 
 def lupp_force_variant(ctx: Context, variant: int, lanes: int = 0, wpb: int = 0) -> int:

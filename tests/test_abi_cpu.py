@@ -97,3 +97,29 @@ def test_null_context_rejected():
 
     rc = L.lupp_batched_solve(Fake(), 8, 1, 0, 0x1000, 8, 64, 0x1000, 8, 0x1000, 0x1000, 0, 0)
     assert rc == -1
+
+
+def test_ragged_lane_counts_without_device():
+    """The lane counts the ragged kernels hold for each size: every size has
+    the thread path or a segment width, the default table's choice among them,
+    and nothing beyond 32 lanes or outside 1..32."""
+    import paper_2609_15217_amd.lupp as L
+
+    class Fake:
+        handle = ctypes.c_void_p(0)
+
+    for n in range(1, 33):
+        ok = [t for t in (1, 2, 4, 8, 16, 32, 64) if L.lupp_ragged_lanes_supported(n, t)]
+        assert ok, n
+        assert 64 not in ok
+        # a segment never has more lanes than twice the rows it needs
+        assert all(t == 1 or t < 2 * n for t in ok), (n, ok)
+        if n > 16:
+            assert ok == [16]
+        default = 1 if n <= 5 else (8 if n <= 16 else 16)
+        assert default in ok
+    assert L.lupp_ragged_lanes_supported(0, 1) == 0
+    assert L.lupp_ragged_lanes_supported(33, 16) == 0
+    assert L.lupp_set_ragged_lanes(Fake(), 8, 8) == -1
+    assert L.lupp_get_ragged_lanes(Fake(), 8) == -1
+    assert L.lupp_autotune_ragged(Fake(), 8, 10, 0x1000, 0x1000, stream=0)[0] == -1

@@ -110,3 +110,58 @@ def test_full_size_mixed_batch_sampled(L, ctx):
         assert np.array_equal(got["ipiv"][ob:ob + n], r["ipiv"][0])
         assert np.array_equal(got["x"][ob:ob + n], r["x"][0])
         assert np.array_equal(got["LU"][oa:oa + n * n], r["LU"][0].reshape(-1))
+
+
+def _supported(L, n):
+    return [t for t in (1, 2, 4, 8, 16, 32) if L.lupp_ragged_lanes_supported(n, t)]
+
+
+@pytest.mark.parametrize("rot", [0, 1, 2])
+def test_every_ragged_lane_count_bitwise(L, ctx, rot):
+    """Every lane count the ragged kernels hold for a size gives the oracle's
+    bits, in both schedules: size n uses its (rot mod k)-th supported count."""
+    saved = {n: L.lupp_get_ragged_lanes(ctx, n) for n in range(1, 33)}
+    try:
+        for n in range(1, 33):
+            ok = _supported(L, n)
+            assert L.lupp_set_ragged_lanes(ctx, n, ok[rot % len(ok)]) == 0
+            assert L.lupp_get_ragged_lanes(ctx, n) == ok[rot % len(ok)]
+        mx = mixed_systems(2500, seed=340 + rot, nmin=1, nmax=32, kappa_max=None)
+        ref = oracle.gesv_ragged(mx["n"], mx["offA"], mx["offB"], mx["A"], mx["b"], threads=8)
+        same(ref, run(L, ctx, mx))
+        same(ref, run(L, ctx, mx, L.LUPP_RAGGED_PER_SIZE))
+    finally:
+        for n, t in saved.items():
+            assert L.lupp_set_ragged_lanes(ctx, n, t) == 0
+
+
+def test_ragged_lane_table_arguments(L, ctx):
+    assert L.lupp_set_ragged_lanes(ctx, 0, 1) == -2
+    assert L.lupp_set_ragged_lanes(ctx, 33, 16) == -2
+    assert L.lupp_set_ragged_lanes(ctx, 20, 8) == -3
+    assert L.lupp_set_ragged_lanes(ctx, 20, 32) == -3
+    assert L.lupp_set_ragged_lanes(ctx, 8, 64) == -3
+    assert L.lupp_get_ragged_lanes(ctx, 0) == -2
+    for n in range(1, 33):
+        assert L.lupp_get_ragged_lanes(ctx, n) in _supported(L, n)
+
+
+def test_autotune_ragged_picks_a_supported_count(L, ctx):
+    from workloads import device_systems
+    n, batch = 20, 3000
+    A, b = device_systems(n, batch, seed=77)
+    A0, b0 = A.clone(), b.clone()
+    saved = L.lupp_get_ragged_lanes(ctx, n)
+    try:
+        rc, lanes, ms = L.lupp_autotune_ragged(ctx, n, batch, A, b, reps=2)
+        assert rc == 0, L.lupp_error_string(rc)
+        assert lanes in _supported(L, n) and ms > 0
+        assert L.lupp_get_ragged_lanes(ctx, n) == lanes
+        torch.cuda.synchronize()
+        assert torch.equal(A, A0) and torch.equal(b, b0)  # inputs are only read
+        assert L.lupp_autotune_ragged(ctx, 0, batch, A, b)[0] == -2
+        assert L.lupp_autotune_ragged(ctx, n, 0, A, b)[0] == -3
+        assert L.lupp_autotune_ragged(ctx, n, batch, None, b)[0] == -4
+        assert L.lupp_autotune_ragged(ctx, n, batch, A, b, reps=0)[0] == -6
+    finally:
+        assert L.lupp_set_ragged_lanes(ctx, n, saved) == 0
