@@ -15,14 +15,25 @@ __global__ void k_ragged_zero(RaggedPlan *plan)
     if (i == 0) plan->bad = 0;
 }
 
+/* Grouping by size. Workgroup g owns the contiguous chunk of systems
+ * [g*chunk, (g+1)*chunk), chunk a multiple of 256: a few hundred workgroups,
+ * so the per-size global atomics (one per workgroup and size) stay few. */
+__device__ __forceinline__ void ragged_chunk(const RaggedArgs &a, int64_t &c0, int64_t &c1)
+{
+    const int64_t chunk = ((a.batch + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+    c0 = (int64_t)blockIdx.x * chunk;
+    c1 = c0 + chunk < a.batch ? c0 + chunk : a.batch;
+}
+
 /* size histogram, privatised in LDS */
 __global__ void __launch_bounds__(256) k_ragged_hist(RaggedArgs a)
 {
     __shared__ int h[34];
     if (threadIdx.x < 34) h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < a.batch) {
+    int64_t c0, c1;
+    ragged_chunk(a, c0, c1);
+    for (int64_t s = c0 + threadIdx.x; s < c1; s += blockDim.x) {
         const int n = a.n[s];
         atomicAdd(&h[(n >= 1 && n <= 32) ? n : 0], 1);
     }
@@ -54,8 +65,9 @@ __global__ void k_ragged_plan(RaggedArgs a)
     plan->next_small = plan->large_items;
 }
 
-/* scatter system indices into their bins: each workgroup reserves one range
- * per size with a single global atomic */
+/* scatter system indices into their bins: each workgroup counts its chunk,
+ * reserves one range per size with a single global atomic, then places its
+ * systems (the order inside a bin does not matter: systems are independent) */
 __global__ void __launch_bounds__(256) k_ragged_scatter(RaggedArgs a)
 {
     __shared__ int cnt[33], base[33], fill[33];
@@ -64,25 +76,24 @@ __global__ void __launch_bounds__(256) k_ragged_scatter(RaggedArgs a)
         fill[threadIdx.x] = 0;
     }
     __syncthreads();
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int n = 0;
-    if (s < a.batch) {
-        n = a.n[s];
-        if (n < 1 || n > 32) {
-            a.info[s] = -1;
-            n = 0;
-        } else {
-            atomicAdd(&cnt[n], 1);
-        }
+    int64_t c0, c1;
+    ragged_chunk(a, c0, c1);
+    for (int64_t s = c0 + threadIdx.x; s < c1; s += blockDim.x) {
+        const int n = a.n[s];
+        if (n >= 1 && n <= 32) atomicAdd(&cnt[n], 1);
+        else a.info[s] = -1;
     }
     __syncthreads();
     if (threadIdx.x >= 1 && threadIdx.x <= 32)
         base[threadIdx.x] =
             cnt[threadIdx.x] ? atomicAdd(&a.plan->cursor[threadIdx.x], cnt[threadIdx.x]) : 0;
     __syncthreads();
-    if (n != 0) {
-        const int p = atomicAdd(&fill[n], 1);
-        a.sorted[a.plan->bin_start[n] + base[n] + p] = (int32_t)s;
+    for (int64_t s = c0 + threadIdx.x; s < c1; s += blockDim.x) {
+        const int n = a.n[s];
+        if (n >= 1 && n <= 32) {
+            const int p = atomicAdd(&fill[n], 1);
+            a.sorted[a.plan->bin_start[n] + base[n] + p] = (int32_t)s;
+        }
     }
 }
 
@@ -128,7 +139,9 @@ int ragged_launch_impl(RaggedWs *ws, const uint8_t *lanes, int64_t batch, const 
     }
     RaggedArgs a{batch, n, offA, offB, A, b, ipiv, info, factors ? 1 : 0, ws->sorted, ws->plan, {}};
     for (int m = 0; m <= 32; ++m) a.lanes[m] = m >= 1 ? lanes[m] : 1;
-    const unsigned blocks = (unsigned)((batch + 255) / 256);
+    /* grouping grid: at most 1024 workgroups of 256 threads, each a chunk */
+    const int64_t full = (batch + 255) / 256;
+    const unsigned blocks = (unsigned)(full < 1024 ? full : 1024);
     hipLaunchKernelGGL(k_ragged_zero, dim3(1), dim3(64), 0, st, ws->plan);
     hipLaunchKernelGGL(k_ragged_hist, dim3(blocks), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_ragged_plan, dim3(1), dim3(64), 0, st, a);
