@@ -489,8 +489,11 @@ __device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) /
  * the trailing update runs under the exec mask of the trailing rows
  * (pos > k). No LDS allocation is needed. lanes_getrf_solve_x also calls
  * x_sink(j, x_j) in every lane for every solution entry; tile / thresh
- * select the pivoting rule (see thread_getrf_solve). */
-template <int N, int T, bool kFMA = false, bool kTile = false, typename IpivSink,
+ * select the pivoting rule (see thread_getrf_solve). CH is the number of
+ * pivot-row columns broadcast (and held in registers) at a time within a
+ * step: larger chunks expose more independent broadcasts per wait at the
+ * cost of 2*CH VGPRs. Results do not depend on it. */
+template <int N, int T, bool kFMA = false, bool kTile = false, int CH = 8, typename IpivSink,
           typename XSink>
 __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][N],
                                                    double (&b)[(N + T - 1) / T],
@@ -499,7 +502,7 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
                                                    double thresh = 0.0)
 {
     constexpr int K = lanes_shape<N, T>::K;
-    constexpr int CH = 8; /* pivot-row columns broadcast per chunk */
+    static_assert(CH >= 1, "CH: pivot-row columns broadcast per chunk");
     const int lane_in_seg = (int)__lane_id() - seg_base;
     int info = 0;
     static_for<0, N>(LUPP_SF(kc) {
@@ -587,14 +590,14 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
     return info;
 }
 
-template <int N, int T, bool kFMA = false, bool kTile = false, typename IpivSink>
+template <int N, int T, bool kFMA = false, bool kTile = false, int CH = 8, typename IpivSink>
 __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N],
                                                  double (&b)[(N + T - 1) / T],
                                                  int (&pos)[(N + T - 1) / T], int seg_base,
                                                  IpivSink ipiv_k, int tile = 0, double thresh = 0.0)
 {
-    return lanes_getrf_solve_x<N, T, kFMA, kTile>(a, b, pos, seg_base, ipiv_k, [](int, double) {},
-                                                  tile, thresh);
+    return lanes_getrf_solve_x<N, T, kFMA, kTile, CH>(a, b, pos, seg_base, ipiv_k,
+                                                      [](int, double) {}, tile, thresh);
 }
 
 }  // namespace lupp

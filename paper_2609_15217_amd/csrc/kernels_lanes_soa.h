@@ -52,6 +52,11 @@ struct soa_shape {
     static constexpr int NCH = (N + CJ - 1) / CJ;        /* chunks */
     /* 512-thread workgroups (T = 32) need two per CU: at most 128 VGPRs */
     static constexpr int MIN_WAVES_EU = WPB >= 8 ? 4 : 1;
+    /* pivot-row broadcast chunk: 16 columns where the kernel runs 2 waves
+     * per SIMD anyway (n >= 26 with 16 lanes; measured n = 32: 6.8 vs
+     * 7.1 ms), 8 below, where 16 would cost a wave per SIMD (n = 24: 4.4 vs
+     * 3.6 ms) */
+    static constexpr int CH = (T == 16 && N >= 26) ? 16 : 8;
     static_assert(NT == S * T, "shape");
 };
 
@@ -165,7 +170,7 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
     constexpr int KP = (N + T - 1) / T;
     int pv[KP];
     static_for<0, KP>(LUPP_SF(sc) { pv[decltype(sc)::value] = 0; });
-    const int inf = lanes_getrf_solve<N, T, F, Tl>(m, x, pos, g * T, [&](int k, int val) {
+    const int inf = lanes_getrf_solve<N, T, F, Tl, Sh::CH>(m, x, pos, g * T, [&](int k, int val) {
         const int c = k / T;
         static_for<0, KP>(LUPP_SF(sc) {
             constexpr int cc = decltype(sc)::value;
