@@ -132,7 +132,10 @@ __device__ __forceinline__ void ragged_item(const RaggedArgs &a, int first, int 
         constexpr int KP = (N + T - 1) / T;
         int pv[KP];
         static_for<0, KP>([&](auto sc) __attribute__((always_inline)) { pv[decltype(sc)::value] = 0; });
-        const int inf = lanes_getrf_solve<N, T>(m, x, pos, g * T, [&](int k, int v) {
+        /* 16-column pivot-row broadcasts where 16-lane segments already need
+         * more than 168 VGPRs (n >= 26), as in the SoA kernels */
+        constexpr int CH = (T == 16 && N >= 26) ? 16 : 8;
+        const int inf = lanes_getrf_solve<N, T, false, false, CH>(m, x, pos, g * T, [&](int k, int v) {
             const int c = k / T;
             static_for<0, KP>([&](auto sc) __attribute__((always_inline)) {
                 constexpr int cc = decltype(sc)::value;
