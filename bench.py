@@ -557,6 +557,14 @@ def main():
                                        "updates_per_s": round(count / (ms * 1e-3)),
                                        "newton_iterations_per_s": round(its / (ms * 1e-3)),
                                        "mean_solves_per_point": round(its / count, 3),
+                                       # FP64 rate of the linear solves alone (dgesv flops of
+                                       # an n x n system per Newton iteration; the law's
+                                       # residual, Jacobian, pow and sqrt are not counted)
+                                       "solve_fp64_TFLOPs": round(
+                                           its * flops_per_system(kind) / (ms * 1e-3) / 1e12, 3),
+                                       "solve_fp64_frac": round(
+                                           its * flops_per_system(kind) / (ms * 1e-3) / 1e12
+                                           / FP64_PEAK_TFLOPS, 4),
                                        "converged": conv,
                                        "default_lanes_per_point": default_lanes,
                                        "mapping": mapping,
