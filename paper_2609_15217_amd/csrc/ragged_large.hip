@@ -3,7 +3,7 @@
 
 namespace lupp {
 
-/* Sizes 17..32 (items 0 .. large_items-1): 16-lane segments need up to ~220
+/* Sizes 17..32 (items 0 .. large_items-1): 16-lane segments need up to ~240
  * VGPRs, so this kernel runs 2 waves per SIMD. */
 __global__ void __launch_bounds__(kRaggedThreads) __attribute__((amdgpu_waves_per_eu(2)))
     k_ragged_large(RaggedArgs a)
