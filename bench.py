@@ -210,8 +210,8 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: every system and integration point is independent, "
-              "so the path runs on one GPU's share; runs on more than one GPU are not part of "
-              "this build.", flush=True)
+              "so the path runs on one GPU's share; multi-GPU execution is not implemented.",
+              flush=True)
         sys.exit(2)
 
     import torch

@@ -18,7 +18,7 @@
  *     stream): results are valid once that stream's work completes.
  *   - Return value: 0 on success; -k if the k-th argument is invalid (nothing
  *     is enqueued, nothing is printed); LUPP_E_UNSUPPORTED for a valid request
- *     this build cannot serve; LUPP_E_HIP_BASE - e for a HIP runtime error e.
+ *     no compiled kernel serves; LUPP_E_HIP_BASE - e for a HIP runtime error e.
  *     No C++ exception crosses the ABI.
  *   - Numerics (strict mode): IEEE binary64, no FMA contraction, true
  *     divisions. Results are bitwise identical to the textbook algorithm's

@@ -478,7 +478,7 @@ const char *lupp_error_string(int code)
 {
     static thread_local char buf[96];
     if (code == 0) return "success";
-    if (code == LUPP_E_UNSUPPORTED) return "request not supported by this build";
+    if (code == LUPP_E_UNSUPPORTED) return "request not supported by the compiled kernels";
     if (code == LUPP_E_NOMEM) return "out of memory";
     if (code <= LUPP_E_HIP_BASE) {
         std::snprintf(buf, sizeof(buf), "HIP error %d: %s", LUPP_E_HIP_BASE - code,
