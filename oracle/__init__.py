@@ -67,8 +67,8 @@ def lib():
         L.oracle_gesv_ragged.restype = None
         L.oracle_law_eval.argtypes = [P, P, P, P, P, P, P]
         L.oracle_law_eval.restype = None
-        L.oracle_constitutive_update.argtypes = [P, i64, P, P, P, P, P, P, P, ctypes.c_double,
-                                                 ctypes.c_int, ctypes.c_int]
+        L.oracle_constitutive_update.argtypes = [P, i64, P, P, P, P, P, P, P, P,
+                                                 ctypes.c_double, ctypes.c_int, ctypes.c_int]
         L.oracle_constitutive_update.restype = None
         _ = i32
         _lib = L
@@ -201,11 +201,14 @@ def law_eval(law: Law, deps, state_t, y):
 
 def constitutive_update(law: Law, deps: np.ndarray, state: np.ndarray | None = None,
                         tol: float = 1e-12, maxit: int = 20, threads: int | None = None,
-                        tangent: bool = False):
+                        tangent: bool = False, want_y: bool = False):
     """Newton update of every point. deps (count, 6); state (count, kind) or None
     for the virgin state. Returns dict(sig, state, iters, status, resid), plus
     tangent (count, 6, 6) = dsig/d(deps) at converged points (NaN elsewhere)
-    when tangent=True."""
+    when tangent=True, and y (count, kind) = the unknowns of the returned
+    iterate when want_y=True (with tol = 0 every point stops after exactly
+    maxit solves, unless a zero pivot or a non-finite residual stops it
+    earlier)."""
     d = _f64(deps)
     count = d.shape[0]
     st = np.zeros((count, law.kind)) if state is None else _f64(state).copy()
@@ -214,11 +217,15 @@ def constitutive_update(law: Law, deps: np.ndarray, state: np.ndarray | None = N
     status = np.zeros(count, dtype=np.int32)
     resid = np.zeros(count)
     tan = np.full((count, 6, 6), np.nan) if tangent else None
+    y = np.full((count, law.kind), np.nan) if want_y else None
     cl = law.c()
     lib().oracle_constitutive_update(ctypes.byref(cl), count, _p(d), _p(st), _p(sig), _p(iters),
-                                     _p(status), _p(resid), _p(tan) if tangent else None, tol,
-                                     maxit, threads or default_threads())
+                                     _p(status), _p(resid), _p(tan) if tangent else None,
+                                     _p(y) if want_y else None, tol, maxit,
+                                     threads or default_threads())
     out = {"sig": sig, "state": st, "iters": iters, "status": status, "resid": resid}
     if tangent:
         out["tangent"] = tan
+    if want_y:
+        out["y"] = y
     return out

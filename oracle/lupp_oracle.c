@@ -392,7 +392,7 @@ static void oracle_tangent(const oracle_law *law, double *J, double *tan)
 
 static void oracle_newton_point(const oracle_law *law, const double *deps, double *state,
                                 double *sig, int32_t *iters, int32_t *status, double *resid,
-                                double *tan, double tol, int maxit)
+                                double *tan, double *yout, double tol, int maxit)
 {
     const int nunk = law->kind;
     double y[13], F[13], J[169], dx[13];
@@ -433,6 +433,8 @@ static void oracle_newton_point(const oracle_law *law, const double *deps, doubl
     *resid = nrm;
     /* J holds the (unfactored) Jacobian of the converged iterate */
     if (st == 0 && tan != NULL) oracle_tangent(law, J, tan);
+    if (yout != NULL)
+        for (int i = 0; i < nunk; ++i) yout[i] = y[i];
     if (st == 0)
         for (int i = 0; i < nunk; ++i) state[i] = state[i] + y[i];
 }
@@ -440,7 +442,7 @@ static void oracle_newton_point(const oracle_law *law, const double *deps, doubl
 typedef struct {
     const oracle_law *law;
     const double *deps;
-    double *state, *sig, *resid, *tan;
+    double *state, *sig, *resid, *tan, *yout;
     int32_t *iters, *status;
     double tol;
     int maxit;
@@ -453,14 +455,15 @@ static void newton_body(void *p, int64_t lo, int64_t hi)
     for (int64_t s = lo; s < hi; ++s)
         oracle_newton_point(c->law, c->deps + 6 * s, c->state + nunk * s, c->sig + 6 * s,
                             c->iters + s, c->status + s, c->resid + s,
-                            c->tan ? c->tan + 36 * s : NULL, c->tol, c->maxit);
+                            c->tan ? c->tan + 36 * s : NULL, c->yout ? c->yout + nunk * s : NULL,
+                            c->tol, c->maxit);
 }
 
 void oracle_constitutive_update(const oracle_law *law, int64_t count, const double *deps,
                                 double *state, double *sig, int32_t *iters,
-                                int32_t *status, double *resid, double *tangent, double tol,
-                                int maxit, int nthreads)
+                                int32_t *status, double *resid, double *tangent, double *yout,
+                                double tol, int maxit, int nthreads)
 {
-    newton_ctx c = {law, deps, state, sig, resid, tangent, iters, status, tol, maxit};
+    newton_ctx c = {law, deps, state, sig, resid, tangent, yout, iters, status, tol, maxit};
     oracle_parallel_for(count, nthreads, newton_body, &c);
 }

@@ -102,11 +102,14 @@ void oracle_law_eval(const oracle_law *law, const double *deps, const double *st
  * residual. tangent: NULL, or [count][36] receiving the consistent tangent
  * dsig/d(deps) (row-major 6x6, Kelvin) of every converged point (Section
  * 2.5; Section 4.3: a multi-right-hand-side solve with the factors of the
- * Jacobian at the converged iterate); other points' entries are untouched. */
+ * Jacobian at the converged iterate); other points' entries are untouched.
+ * yout: NULL, or [count][kind] receiving the unknowns (increments) of the
+ * returned iterate, whatever the status (a side output for comparisons at a
+ * given iterate: with tol = 0 the loop stops after exactly maxit solves). */
 void oracle_constitutive_update(const oracle_law *law, int64_t count, const double *deps,
                                 double *state, double *sig, int32_t *iters,
-                                int32_t *status, double *resid, double *tangent, double tol,
-                                int maxit, int nthreads);
+                                int32_t *status, double *resid, double *tangent, double *yout,
+                                double tol, int maxit, int nthreads);
 
 #ifdef __cplusplus
 }

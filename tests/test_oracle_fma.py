@@ -8,7 +8,12 @@ which re-runs its elimination:
 * on random systems the pivots equal LAPACK's and the solutions agree with
   LAPACK's to the rounding level; P A = L U; backward error O(n u);
 * the mode really changes the arithmetic: results differ from strict mode in
-  the last bits for most random systems.
+  the last bits for most random systems;
+* 2 x 2 systems whose fused and unfused results are known in closed form,
+  one for each place a multiply-subtract occurs (the Schur update, the
+  forward and the back substitution): with l = 1 - 2^-30 and u = 1 + 2^-30,
+  l * u = 1 - 2^-60 exactly, which rounds to 1, so 1 - l*u is 0 in strict
+  mode and 2^-60 in FMA mode.
 """
 import numpy as np
 import pytest
@@ -69,3 +74,46 @@ def test_against_lapack(n):
         assert r <= 16 * n * 2.2e-16 * (np.abs(M).sum(axis=1).max() * scale + np.abs(b[s]).max())
         differ += not np.array_equal(got["x"][s], strict["x"][s])
     assert differ > 150  # fused arithmetic changes the last bits
+
+
+E30, E60 = 2.0 ** -30, 2.0 ** -60
+
+
+def _solve2(rows, rhs, fma):
+    """One 2 x 2 system given row-major; returns the oracle's LU (row-major),
+    x, ipiv and info."""
+    A = np.array(rows, dtype=float).T[None].copy()  # column-major storage
+    b = np.array(rhs, dtype=float)[None]
+    out = oracle.gesv_batch_mode(A, b, fma=fma, threads=1)
+    return out["LU"][0].T, out["x"][0], out["ipiv"][0], int(out["info"][0])
+
+
+@pytest.mark.parametrize("fma", [False, True])
+def test_closed_form_forward_substitution(fma):
+    l, y0 = 1.0 - E30, 1.0 + E30
+    LU, x, piv, info = _solve2([[1.0, 0.0], [l, 1.0]], [y0, 1.0], fma)
+    assert info == 0 and list(piv) == [1, 2]
+    assert LU[1, 0] == l and LU[1, 1] == 1.0
+    assert x[0] == y0
+    assert x[1] == (E60 if fma else 0.0)
+
+
+@pytest.mark.parametrize("fma", [False, True])
+def test_closed_form_back_substitution(fma):
+    u, x1 = 1.0 - E30, 1.0 + E30
+    LU, x, piv, info = _solve2([[1.0, u], [0.0, 1.0]], [1.0, x1], fma)
+    assert info == 0 and list(piv) == [1, 2]
+    assert x[1] == x1
+    assert x[0] == (E60 if fma else 0.0)
+
+
+@pytest.mark.parametrize("fma", [False, True])
+def test_closed_form_schur_update(fma):
+    l, u = 1.0 - E30, 1.0 + E30
+    LU, x, piv, info = _solve2([[1.0, u], [l, 1.0]], [1.0, 1.0], fma)
+    assert list(piv) == [1, 2] and LU[1, 0] == l
+    if fma:
+        assert info == 0 and LU[1, 1] == E60
+    else:
+        assert info == 2 and LU[1, 1] == 0.0
+        assert list(x) == [1.0, 1.0]  # b is left unchanged when info > 0

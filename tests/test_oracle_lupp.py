@@ -179,6 +179,34 @@ def test_reconstruction_and_multiplier_bound(n):
         assert np.abs(R).max() <= bound + 1e-300
 
 
+@pytest.mark.parametrize("n", [2, 3, 5, 8])
+def test_first_column_multipliers_are_correctly_rounded_quotients(n):
+    """Section 2.2's multiplier l_i0 = a_i0 / a_p0 is a true division: after
+    the first interchange, every stored multiplier of column 0 is the
+    correctly rounded quotient of two input entries (exact rationals,
+    rounded once), moved by the later interchanges like the rest of its row.
+    A reciprocal multiply a_i0 * (1 / a_p0) rounds twice and misses it on a
+    sizeable share of entries."""
+    A, b, _ = systems(n, 400, seed=450 + n)
+    out = oracle.gesv_batch(A, b, threads=4)
+    mism = 0
+    for s in range(A.shape[0]):
+        col = [Fraction(float(v)) for v in A[s][0]]  # column 0, rows 0..n-1
+        ipiv = out["ipiv"][s]
+        p0 = ipiv[0] - 1
+        rows = list(range(n))
+        rows[0], rows[p0] = rows[p0], rows[0]
+        mult = [float(col[rows[i]] / col[p0]) for i in range(n)]  # Fraction -> float rounds once
+        for k in range(1, n):
+            r = ipiv[k] - 1
+            mult[k], mult[r] = mult[r], mult[k]
+        got = out["LU"][s][0][1:]
+        assert np.array_equal(got, np.array(mult[1:])), s
+        recip = 1.0 / float(col[p0])
+        mism += sum(float(col[rows[i]]) * recip != float(col[rows[i]] / col[p0]) for i in range(1, n))
+    assert mism > 0  # the reciprocal form really differs on these inputs
+
+
 @pytest.mark.parametrize("n", [1, 2, 4, 8, 16, 32])
 def test_special_matrices(n):
     sm = special_matrices(n, seed=n)

@@ -38,6 +38,16 @@ MUTANTS = {
     "tiled_no_fallback": ("if (fabs(col[p]) < thresh) {", "if (0) {"),
     "tiled_threshold_inverted": ("if (fabs(col[p]) < thresh) {", "if (fabs(col[p]) > thresh) {"),
     "tiled_tile_end": ("int k1 = (k / ts + 1) * ts;", "int k1 = (k / ts + 1) * ts + 1;"),
+    "stop_rule_off_by_one": ("if (k == maxit) {", "if (k + 1 >= maxit) {"),
+    "reciprocal_multipliers": (
+        "a[i + (int64_t)k * lda] = a[i + (int64_t)k * lda] / a[k + (int64_t)k * lda];",
+        "a[i + (int64_t)k * lda] = a[i + (int64_t)k * lda] * (1.0 / a[k + (int64_t)k * lda]);"),
+    "fma_forward_substitution_unfused": (
+        "for (int i = j + 1; i < n; ++i)\n            b[i] = oracle_msub(b[i], lu[i + (int64_t)j * lda], b[j], use_fma);",
+        "for (int i = j + 1; i < n; ++i)\n            b[i] = oracle_msub(b[i], lu[i + (int64_t)j * lda], b[j], 0);"),
+    "fma_back_substitution_unfused": (
+        "for (int i = 0; i < j; ++i)\n            b[i] = oracle_msub(b[i], lu[i + (int64_t)j * lda], b[j], use_fma);",
+        "for (int i = 0; i < j; ++i)\n            b[i] = oracle_msub(b[i], lu[i + (int64_t)j * lda], b[j], 0);"),
 }
 
 

@@ -211,6 +211,40 @@ def test_objectivity(kind):
     assert rel.max() <= 1e-10
 
 
+def test_stop_rule_counts_linear_solves():
+    """maxit is the number of linear solves (the residual is tested at
+    x_0 .. x_maxit). With A = 0 the law is linear and elastic: the first
+    Newton step solves it exactly (J = [[I, N], [0, 1]], F(x_1) = 0 in
+    floating point), so maxit = 1 converges in one solve while maxit = 0
+    stops before any solve."""
+    deps = newton_points(50, seed=19)
+    law = Law(kind=7, A=0.0)
+    one = oracle.constitutive_update(law, deps, maxit=1, threads=2)
+    assert np.all(one["status"] == 0) and np.all(one["iters"] == 1)
+    assert np.all(one["resid"] == 0.0)
+    assert np.array_equal(one["state"][:, :6], deps) and np.all(one["state"][:, 6] == 0)
+    zero = oracle.constitutive_update(law, deps, maxit=0, threads=2)
+    assert np.all(zero["status"] == 1) and np.all(zero["iters"] == 0)
+    assert np.all(zero["state"] == 0)
+    # a point that stops on the cap has made exactly maxit solves, and a
+    # point that converges under a cap converges identically without it
+    deps = newton_points(400, seed=20)
+    for kind in (7, 13):
+        free = oracle.constitutive_update(Law(kind=kind), deps, maxit=60, threads=4)
+        assert np.all(free["status"] == 0)
+        for maxit in (1, 2, 5, 12):
+            cap = oracle.constitutive_update(Law(kind=kind), deps, maxit=maxit, threads=4)
+            hit = cap["status"] == 1
+            assert hit.any()
+            assert np.all(cap["iters"][hit] == maxit)
+            assert np.all(free["iters"][hit] > maxit)
+            conv = cap["status"] == 0
+            assert np.all(cap["iters"][conv] <= maxit)
+            assert np.array_equal(cap["iters"][conv], free["iters"][conv])
+            assert np.array_equal(cap["sig"][conv], free["sig"][conv])
+            assert np.all(cap["state"][hit] == 0)  # not committed
+
+
 def test_stop_rule_maxit_and_nonfinite():
     deps = newton_points(200, seed=18)
     out = oracle.constitutive_update(Law(kind=7), deps, maxit=1, threads=2)
