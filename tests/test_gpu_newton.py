@@ -1,11 +1,9 @@
 """GPU parity of the fused Newton constitutive update (Section 2.1, Algorithm 2)
-against the CPU oracle.
-
-Status must agree exactly. Iteration counts must agree except where the two
-residual histories straddle the tolerance (a near-tie: the solvers' rounding
-differs at the last bits, e.g. in pow); where status and iterations agree the
-stress must match to 1e-10 relative (infinity norm) and the committed state to
-the same relative level.
+against the CPU oracle, every point checked (tests/newton_check.py): where
+status and iteration count agree, the stress and the committed state within
+1e-10 relative (infinity norm); statuses 2 and 3 exactly; every other point
+must be a near-tie (the oracle's residual within a few percent of tol at the
+deciding iterate) and is compared at the GPU's own iterate to 1e-10.
 """
 import numpy as np
 import pytest
@@ -13,6 +11,7 @@ import torch
 
 import oracle
 from oracle import Law
+from newton_check import check_newton
 from workloads import newton_points
 
 pytestmark = pytest.mark.gpu
@@ -56,30 +55,20 @@ def gpu_update(L, ctx, law: Law, deps, state=None, tol=1e-12, maxit=20, pad=0, t
     return out
 
 
-def compare(o, g, rel=1e-10, min_agree=0.999):
-    assert np.array_equal(o["status"], g["status"])
-    same = o["iters"] == g["iters"]
-    assert same.mean() >= min_agree, same.mean()
-    assert np.all(np.abs(o["iters"] - g["iters"]) <= 1)
-    ok = same & (o["status"] == 0)
-    s_o, s_g = o["sig"][ok], g["sig"][ok]
-    scale = np.maximum(np.abs(s_o).max(axis=1), 1e-300)
-    assert (np.abs(s_o - s_g).max(axis=1) / scale).max() <= rel
-    st_o, st_g = o["state"][ok], g["state"][ok]
-    scale = np.maximum(np.abs(st_o).max(axis=1), 1e-300)
-    assert (np.abs(st_o - st_g).max(axis=1) / scale).max() <= rel
-    bad = o["status"] != 0
-    assert np.array_equal(o["state"][bad], g["state"][bad])  # not committed
-    return ok
+def as_dict(st, sig, it, ss, tan=None):
+    """Outputs of run_update (component-major device copies) as per-point arrays."""
+    out = {"state": st.T, "sig": sig.T, "iters": it, "status": ss}
+    if tan is not None:
+        out["tangent"] = tan.T.reshape(-1, 6, 6)
+    return out
 
 
 @pytest.mark.parametrize("kind", [7, 13])
 def test_benchmark_law_parity(L, ctx, kind):
     deps = newton_points(20000, seed=4)
     law = Law(kind=kind)
-    o = oracle.constitutive_update(law, deps, threads=8)
     g = gpu_update(L, ctx, law, deps, pad=37)
-    compare(o, g)
+    check_newton(law, deps, None, 1e-12, 20, g)
     assert np.all(g["pad_sig"] != g["pad_sig"])  # padding untouched (still NaN)
     assert np.all(g["pad_state"] == 0)
 
@@ -96,9 +85,8 @@ def test_non_virgin_states_and_tight_tolerance(L, ctx, kind):
         a[:, :3] -= a[:, :3].mean(axis=1, keepdims=True)
         st[:, 7:] = a
     law = Law(kind=kind)
-    o = oracle.constitutive_update(law, deps, st, tol=1e-14, maxit=40, threads=8)
     g = gpu_update(L, ctx, law, deps, st, tol=1e-14, maxit=40)
-    compare(o, g)
+    check_newton(law, deps, st, 1e-14, 40, g)
 
 
 @pytest.mark.parametrize("kind", [7, 13])
@@ -115,18 +103,22 @@ def test_stop_rules(L, ctx, kind):
     assert g["status"][0] == 0 and g["iters"][0] == 0
     assert g["status"][1] == 3 and g["status"][2] == 3
     assert (g["status"] == 1).mean() > 0.9
+    assert np.all(g["iters"][g["status"] == 1] == 1)
+    check_newton(law, deps, None, 1e-12, 1, g)
     o = oracle.constitutive_update(law, deps, maxit=0, threads=4)
     g = gpu_update(L, ctx, law, deps, maxit=0)
     assert np.array_equal(o["status"], g["status"]) and np.all(g["iters"] == 0)
+    check_newton(law, deps, None, 1e-12, 0, g)
 
 
 def test_elastic_limit(L, ctx):
     law = Law(kind=7, A=0.0)
     deps = newton_points(1000, seed=43)
-    o = oracle.constitutive_update(law, deps, threads=4)
     g = gpu_update(L, ctx, law, deps)
     assert np.all(g["iters"] == 1) and np.all(g["status"] == 0)
-    compare(o, g, rel=1e-14)
+    check_newton(law, deps, None, 1e-12, 20, g, rel=1e-14)
+    g1 = gpu_update(L, ctx, law, deps, maxit=1)  # one solve is enough (exact elastic step)
+    assert np.all(g1["iters"] == 1) and np.all(g1["status"] == 0)
 
 
 def test_empty_and_invalid(L, ctx):
@@ -152,27 +144,24 @@ def test_full_size_sampled(L, ctx, kind):
     rng = np.random.Generator(np.random.PCG64(44))
     idx = np.sort(rng.choice(count, 20000, replace=False))
     idx[-1] = count - 1
-    o = oracle.constitutive_update(law, deps[idx], threads=8)
-    compare(o, {k: v[idx] for k, v in g.items() if not k.startswith("pad")})
+    check_newton(law, deps[idx], None, 1e-12, 20,
+                 {k: v[idx] for k, v in g.items() if not k.startswith("pad")})
     assert (g["status"] == 0).mean() > 0.999
 
 
 @pytest.mark.parametrize("kind", [7, 13])
 def test_consistent_tangent_matches_oracle(L, ctx, kind):
     """Consistent tangent (Section 4.3: a multi-right-hand-side solve after
-    convergence): same points converged, tangents within 1e-9 relative where
-    status and iterations agree; untouched for unconverged points and in the
-    padding; the stress and state are those of the update without tangent."""
+    convergence): every converged point's tangent within 1e-9 relative of the
+    oracle's at the same iterate (near-ties included); untouched for
+    unconverged points and in the padding; the stress and state are those of
+    the update without tangent."""
     law = Law(kind=kind)
     deps = newton_points(3000, seed=60 + kind)
-    o = oracle.constitutive_update(law, deps, maxit=16, threads=8, tangent=True)
     g = gpu_update(L, ctx, law, deps, maxit=16, pad=7, tangent=True)
-    ok = compare(o, g, min_agree=0.99)
+    check_newton(law, deps, None, 1e-12, 16, g, tangent_rel=1e-9)
     conv = g["status"] == 0
     assert conv.mean() > 0.05 and (~conv).any()  # both kinds of points present
-    T_o, T_g = o["tangent"][ok], g["tangent"][ok]
-    rel = np.abs(T_o - T_g).max(axis=(1, 2)) / np.abs(T_o).max(axis=(1, 2))
-    assert rel.max() <= 1e-9, rel.max()
     assert np.all(np.isnan(g["tangent"][~conv]))
     assert np.all(np.isnan(g["pad_tangent"]))
     plain = gpu_update(L, ctx, law, deps, maxit=16)
@@ -230,6 +219,8 @@ def test_batched_newton_is_bitwise_the_fused_update(L, ctx, kind, flags):
         assert np.array_equal(a, b, equal_nan=True)
     iters, status = ref[2], ref[3]
     assert k == iters.max() + 1 + int((status == 2).any())
+    # and against the oracle directly, every point
+    check_newton(law, deps, None, 1e-12, 20, as_dict(*got), tangent_rel=1e-9)
 
 
 def test_batched_newton_edge_cases(L, ctx):
@@ -278,6 +269,7 @@ def test_lanes_per_point_newton_is_bitwise_the_lane_per_point_one(L, ctx, kind, 
             assert L.lupp_set_newton_variant(ctx, kind, 0) == 0
             for a, b in zip(ref, got):
                 assert np.array_equal(a, b, equal_nan=True)
+            check_newton(law, deps, state, 1e-12, maxit, as_dict(*got))
         state = ref[0].T.copy()  # continue from the committed state
     assert L.lupp_set_newton_variant(ctx, 7, 16) == -3
     assert L.lupp_set_newton_variant(ctx, 9, 1) == -2

@@ -8,6 +8,7 @@ import torch
 
 import oracle
 from oracle import Law
+from newton_check import check_newton
 from workloads import newton_points
 
 pytestmark = pytest.mark.gpu
@@ -74,6 +75,9 @@ def test_replays_equal_eager_steps(L, ctx, kind, tangent):
 
 
 def test_steps_follow_the_oracle(L, ctx):
+    """A three-step sweep equals the same steps launched one by one
+    (bitwise), and each step, started from the state the GPU committed at the
+    previous one, passes the every-point Newton parity against the oracle."""
     kind, count, steps = 13, 2000, 3
     law = L.make_law(kind)
     d, host, st, sig, it, ss, _ = buffers(kind, count, count, steps, seed=90)
@@ -81,18 +85,21 @@ def test_steps_follow_the_oracle(L, ctx):
     sw = L.Sweep(ctx, pts, law, 1e-12, 60, steps, 6 * count)
     assert sw.launch() == 0
     torch.cuda.synchronize()
-    state = None
-    for t in range(steps):
-        o = oracle.constitutive_update(Law(kind=kind), host[t], state, maxit=60, threads=8)
-        state = o["state"]
-    conv = o["status"] == 0
-    assert conv.mean() > 0.98
-    assert (ss.cpu().numpy() == o["status"]).mean() > 0.98
-    g = st.cpu().numpy().T
-    both = conv & (ss.cpu().numpy() == 0)
-    rel = np.abs(g[both] - state[both]).max(axis=1) / np.abs(state[both]).max(axis=1)
-    assert np.quantile(rel, 0.99) <= 1e-9
+    final = snapshot(st, sig, it, ss)
     sw.close()
+    # the same steps eagerly, checked one at a time
+    st.zero_()
+    prev = np.zeros((count, kind))
+    for t in range(steps):
+        assert L.constitutive_update(ctx, L.points(d[t], st, sig, it, ss), law, 1e-12, 60) == 0
+        torch.cuda.synchronize()
+        g = {"state": st.cpu().numpy().T.copy(), "sig": sig.cpu().numpy().T.copy(),
+             "iters": it.cpu().numpy().copy(), "status": ss.cpu().numpy().copy()}
+        r = check_newton(Law(kind=kind), host[t], prev, 1e-12, 60, g)
+        assert (g["status"] == 0).mean() > 0.98, r
+        prev = g["state"]
+    for a, b in zip(final, snapshot(st, sig, it, ss)):
+        assert np.array_equal(a, b)
 
 
 def test_same_increment_every_step_and_arguments(L, ctx):
