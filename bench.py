@@ -18,6 +18,7 @@ timed on this host on a bounded sample.
 
 Profiling helpers (for rocprofv3):
     python bench.py --only 32:soa --reps 20     run one (n, layout) kernel only
+    python bench.py --only newton:13 --reps 5   run one fused Newton update only
     python bench.py --copy-calibration          a plain 2 GiB device copy
 """
 from __future__ import annotations
@@ -36,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FP64 systems solved/s (n=8..32) + Newton updates/s; p50/p99 latency"
 SIZES = (4, 8, 12, 16, 24, 32)
+STEP_SIZES = (8, 12, 16, 24, 32)  # the sizes the metric names; n = 4 is reported beside them
 BATCH = 1 << 20
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
@@ -91,38 +93,105 @@ def load_traffic(kernel_key: str):
     return rec.get("bytes_per_launch")
 
 
-def run_serving(L, ctx, torch, dev, seconds: float, rate: float = 2000.0):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_oracle_baseline(host, sizes, newton=True, runs=10):
+    """The CPU oracle as it stands, timed on this host: every core this
+    process may use (the pool's share, at most 16) and one core; one warm-up
+    then `runs` timed runs, median. Bounded samples: the first systems of the
+    sweep's inputs per n, and the first points of the Newton workload."""
+    import oracle
+    from workloads import newton_points
+    cores = min(16, len(os.sched_getaffinity(0)))
+
+    def median_time(fn):
+        fn()
+        ts = []
+        for _ in range(runs):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    def solve_rate(per_n, threads):
+        def go():
+            for n in sizes:
+                A, b = host[n]
+                oracle.gesv_batch(A[:per_n], b[:per_n], threads=threads)
+        return len(sizes) * per_n / median_time(go)
+
+    S_all, S_one = 1 << 18, 1 << 14
+    out = {"value": round(solve_rate(S_all, cores)), "unit": "systems/s", "cores": cores,
+           "kind": "oracle", "model": cpu_model(), "nproc": os.cpu_count(),
+           "median_of": runs, "warmup": 1,
+           "sample": f"first {S_all} systems of each n in {list(sizes)} of the sweep's inputs "
+                     f"(AoS; the oracle has one layout), {cores} threads",
+           "one_core": {"systems_per_s": round(solve_rate(S_one, 1)),
+                        "sample": f"first {S_one} systems of each n, 1 thread"}}
+    if newton:
+        nt = {}
+        for kind in (7, 13):
+            for label, P, th in (("all", 1 << 16, cores), ("one_core", 1 << 12, 1)):
+                deps = newton_points(P, seed=4)
+                dt = median_time(lambda: oracle.constitutive_update(oracle.Law(kind=kind), deps,
+                                                                    threads=th))
+                nt[f"norton{kind}_updates_per_s" + ("" if label == "all" else "_one_core")] = \
+                    round(P / dt)
+        nt["sample"] = "first 65536 (all cores) / 4096 (one core) points of the benchmark increments"
+        out["newton"] = nt
+    return out
+
+
+class ServingPools:
+    """Device-resident request payloads (an upstream GPU producer): seeded
+    random matrices, right-hand sides and strain increments, and output rings,
+    allocated once for every serving run."""
+
+    MAX_SYS, MAX_PTS, SLOTS = 1_000_000, 500_000, 64
+
+    def __init__(self, torch, dev):
+        g = torch.Generator(device=dev)
+        g.manual_seed(5)
+        M, P, S = self.MAX_SYS, self.MAX_PTS, self.SLOTS
+        self.A = torch.randn(M * 32 * 32, generator=g, dtype=torch.float64, device=dev)
+        self.b = torch.randn(M * 32, generator=g, dtype=torch.float64, device=dev)
+        self.d = (torch.rand(6 * P, generator=g, dtype=torch.float64, device=dev) - 0.5) * 4e-3
+        self.x = torch.empty((S, M * 32), dtype=torch.float64, device=dev)
+        self.ip = torch.empty((S, M * 32), dtype=torch.int32, device=dev)
+        self.sig = torch.empty((S, 6 * P), dtype=torch.float64, device=dev)
+        self.its = torch.empty((S, 2 * P), dtype=torch.int32, device=dev)
+
+
+def run_serving(L, ctx, pools, seconds: float, rate: float, mode: int, seed: int = 5):
     """Poisson stream of requests (half solve batches, n ~ U{2..32}, 1k-1M
     systems; half Newton updates of device-resident point sets, 1k-500k
     points, 7x7 or 13x13 law) submitted to the serving loop at their arrival
-    times. Inputs are slices of device-resident random pools (an upstream GPU
-    producer); latency runs from the scheduled arrival to completion."""
+    times for `seconds` of wall time. Latency runs from the scheduled arrival
+    to completion (queueing behind the client's 64 outstanding requests
+    included)."""
     import threading
 
     from workloads import serving_requests
-    reqs = serving_requests(int(rate * seconds) + 1, seed=5, rate=rate)
+    reqs = serving_requests(int(rate * seconds) + 1, seed=seed, rate=rate)
     reqs = [q for q in reqs if q["t"] <= seconds]
-    g = torch.Generator(device=dev)
-    g.manual_seed(5)
-    max_sys, max_pts = 1_000_000, 500_000
-    A_pool = torch.randn(max_sys * 32 * 32, generator=g, dtype=torch.float64, device=dev)
-    b_pool = torch.randn(max_sys * 32, generator=g, dtype=torch.float64, device=dev)
-    d_pool = (torch.rand(6 * max_pts, generator=g, dtype=torch.float64, device=dev) - 0.5) * 4e-3
-    slots = 48
-    x_ring = torch.empty((slots, max_sys * 32), dtype=torch.float64, device=dev)
-    i_ring = torch.empty((slots, max_sys), dtype=torch.int32, device=dev)
-    sig_ring = torch.empty((slots, 6 * max_pts), dtype=torch.float64, device=dev)
-    it_ring = torch.empty((slots, 2 * max_pts), dtype=torch.int32, device=dev)
-    srv = L.Server(ctx, 48 << 30, 16, 8)
+    srv = L.Server(ctx, 48 << 30, 64, 8, mode)
     rng = np.random.Generator(np.random.PCG64(55))
     sets = {7: [], 13: []}
     for kind in (7, 13):
         for _ in range(16):
-            cnt = int(round(np.exp(rng.uniform(np.log(1_000), np.log(max_pts)))))
+            cnt = int(round(np.exp(rng.uniform(np.log(1_000), np.log(pools.MAX_PTS)))))
             sets[kind].append((L.lupp_server_add_points(srv, kind, cnt), cnt))
     laws = {7: L.make_law(7), 13: L.make_law(13)}
     done = []
-    lock = threading.Semaphore(slots)
+    lock = threading.Semaphore(pools.SLOTS)
     tickets = []
     cv = threading.Condition()
 
@@ -144,28 +213,32 @@ def run_serving(L, ctx, torch, dev, seconds: float, rate: float = 2000.0):
     th = threading.Thread(target=collector)
     th.start()
     ms_sys = ms_pts = 0
+    submitted = 0
     t0 = time.perf_counter()
     for k, q in enumerate(reqs):
         now = time.perf_counter() - t0
+        if now > seconds:  # overloaded: stop offering at the end of the window
+            break
         if q["t"] > now:
             time.sleep(q["t"] - now)
         lock.acquire()
-        slot = k % slots
+        slot = k % pools.SLOTS
         if q["kind"] == "solve":
-            n, bsz = q["n"], min(q["size"], max_sys)
-            r = L.solve_request(n, bsz, A_pool.data_ptr(), b_pool.data_ptr(), x_ring[slot].data_ptr(),
-                                None, i_ring[slot].data_ptr())
+            n, bsz = q["n"], min(q["size"], pools.MAX_SYS)
+            r = L.solve_request(n, bsz, pools.A.data_ptr(), pools.b.data_ptr(),
+                                pools.x[slot].data_ptr(), None, pools.ip[slot].data_ptr())
             ms_sys += bsz
         else:
             sid, cnt = sets[q["law"]][int(rng.integers(0, 16))]
-            base = sig_ring[slot].data_ptr()
-            r = L.update_request(sid, cnt, laws[q["law"]], d_pool.data_ptr(), base,
-                                 it_ring[slot].data_ptr(), it_ring[slot].data_ptr() + 4 * max_pts)
+            r = L.update_request(sid, cnt, laws[q["law"]], pools.d.data_ptr(),
+                                 pools.sig[slot].data_ptr(), pools.its[slot].data_ptr(),
+                                 pools.its[slot].data_ptr() + 4 * pools.MAX_PTS)
             ms_pts += cnt
         submit_at = time.perf_counter() - t0
         t = L.lupp_server_submit(srv, r)
         if t <= 0:
             raise RuntimeError(f"serving submit: {L.lupp_error_string(t)}")
+        submitted += 1
         with cv:
             tickets.append((t, q["t"], submit_at, q))
             cv.notify()
@@ -178,19 +251,18 @@ def run_serving(L, ctx, torch, dev, seconds: float, rate: float = 2000.0):
     srv.close()
     lat = np.array([d[1] for d in done if d[0] == 0])
     failed = sum(1 for d in done if d[0] != 0)
-    out = {"workload": "Poisson 2000 req/s for %.0f s: 50%% solve (n~U{2..32}, 1k-1M systems, "
-                       "log-uniform), 50%% Newton update of device-resident point sets (1k-500k "
-                       "points, 7x7/13x13 at 50/50)" % seconds,
-           "requests": len(reqs), "failed": failed, "wall_s": round(wall, 3),
+    out = {"rate_offered": rate, "mode": "merged" if mode == 0 else "per_request",
+           "seconds": seconds, "requests_offered": len(reqs), "requests": submitted,
+           "failed": failed, "wall_s": round(wall, 3),
            "p50_ms": round(float(np.percentile(lat, 50)), 3),
            "p99_ms": round(float(np.percentile(lat, 99)), 3),
            "systems_per_s": round(ms_sys / wall), "updates_per_s": round(ms_pts / wall),
-           "achieved_req_per_s": round(len(reqs) / wall, 1),
-           "peak_inflight": stats["peak_inflight"], "peak_bytes": stats["peak_bytes"],
-           "budget_bytes": stats["budget_bytes"]}
-    log(f"serving: p50 {out['p50_ms']} ms p99 {out['p99_ms']} ms, {out['achieved_req_per_s']} req/s")
-    del A_pool, b_pool, d_pool, x_ring, i_ring, sig_ring, it_ring
-    torch.cuda.empty_cache()
+           "achieved_req_per_s": round(submitted / wall, 1),
+           "passes": stats["passes"], "launches": stats["launches"],
+           "peak_inflight": stats["peak_inflight"], "peak_bytes": stats["peak_bytes"]}
+    log(f"serving {out['mode']} {rate:.0f} req/s x {seconds:.0f} s: p50 {out['p50_ms']} ms "
+        f"p99 {out['p99_ms']} ms, {out['achieved_req_per_s']} req/s, {out['launches']} launches "
+        f"for {submitted} requests")
     return out
 
 
@@ -202,8 +274,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=8.0)
-    ap.add_argument("--only", default=None, help="n:layout, e.g. 32:soa")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-sweep-seconds", type=float, default=5.0)
+    ap.add_argument("--only", default=None,
+                    help="n:layout (e.g. 32:soa) or newton:kind (7 or 13): run that kernel only")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -234,6 +308,26 @@ def main():
         return
 
     ctx = L.Context(0)
+    if args.only and args.only.startswith("newton:"):
+        # one fused Newton update of 2^20 points, `reps` times (profiling)
+        kind = int(args.only.split(":")[1])
+        count = 1 << 20
+        d = torch.from_numpy(newton_points(count, seed=4).T.copy()).to(dev)
+        st = torch.zeros((kind, count), dtype=torch.float64, device=dev)
+        sig = torch.empty((6, count), dtype=torch.float64, device=dev)
+        it = torch.empty(count, dtype=torch.int32, device=dev)
+        stt = torch.empty(count, dtype=torch.int32, device=dev)
+        pts = L.points(d, st, sig, it, stt)
+        law = L.make_law(kind)
+        for r in range(args.reps):
+            st.zero_()
+            rc = L.constitutive_update(ctx, pts, law, 1e-12, 20, stream)
+            if rc != 0:
+                raise RuntimeError(L.lupp_error_string(rc))
+        torch.cuda.synchronize()
+        log(f"--only {args.only}: {args.reps} launches done, mean solves/point "
+            f"{it.double().mean().item():.3f}")
+        return
     sizes = SIZES
     layouts = ("soa", "aos")
     if args.only:
@@ -291,6 +385,10 @@ def main():
         return
 
     # ------------------------------------------------------------- sweep
+    # the timed step: every (n, layout) of n = 8..32; the n = 4 launches are
+    # timed the same way after the steps, outside the step's clock
+    step_keys = [k for k in keys if k[0] in STEP_SIZES]
+    extra_keys = [k for k in keys if k[0] not in STEP_SIZES]
     ev = {k: [] for k in keys}
     for w in range(args.warmup):
         restore()
@@ -303,7 +401,7 @@ def main():
         restore()
         torch.cuda.synchronize()
         t_start = time.perf_counter()
-        for k in keys:
+        for k in step_keys:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
@@ -312,8 +410,16 @@ def main():
             ev[k].append((e0, e1))
         torch.cuda.synchronize()
         total += time.perf_counter() - t_start
+        for k in extra_keys:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            launch(k)
+            e1.record(stream)
+            ev[k].append((e0, e1))
+        torch.cuda.synchronize()
         log(f"step {s + 1}/{args.steps} done")
-    systems_per_step = len(keys) * BATCH
+    systems_per_step = len(step_keys) * BATCH
     value = systems_per_step * args.steps / total
     ms_per_step = 1000.0 * total / args.steps
 
@@ -336,6 +442,11 @@ def main():
                            "GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                            "fp64_TFLOPs": round(tfl, 3),
                            "variant": "thread" if v == 1 else f"lanes{lanes}", "wpb": wpb})
+    extra_ms = sum(r["ms"] for r in per_kernel if r["n"] not in STEP_SIZES)
+    sweep_all = {"sizes": list(sizes), "systems_per_s": round(
+        len(keys) * BATCH / ((ms_per_step + extra_ms) * 1e-3)),
+        "note": "every (n, layout) of the sweep including n = 4: step time plus the n = 4 "
+                "launches' event time"}
     dom = max(per_kernel, key=lambda r: r["ms"])
     dom_key = f"lupp_n{dom['n']}_{dom['layout']}"
     achieved = dom["GBps"]
@@ -387,8 +498,8 @@ def main():
                     tt.append(e0.elapsed_time(e1))
             base = next(r for r in per_kernel if (r["n"], r["layout"]) == k)["ms"]
             fma_mode[f"n{k[0]}_{k[1]}"] = {"ms": round(float(np.mean(tt)), 4), "strict_ms": base}
-        fma_total = sum(v["ms"] for v in fma_mode.values())
-        fma_mode["sweep_systems_per_s"] = round(len(keys) * BATCH / (fma_total * 1e-3))
+        fma_total = sum(v["ms"] for kk, v in fma_mode.items() if int(kk[1:].split("_")[0]) in STEP_SIZES)
+        fma_mode["sweep_systems_per_s"] = round(len(step_keys) * BATCH / (fma_total * 1e-3))
         log(f"FMA mode: {fma_mode}")
 
     # ------------------------------------------------------------- ragged
@@ -447,7 +558,20 @@ def main():
     # ------------------------------------------------------------- serving
     serving = {}
     if args.serve_seconds > 0:
-        serving = run_serving(L, ctx, torch, dev, args.serve_seconds)
+        pools = ServingPools(torch, dev)
+        main_run = run_serving(L, ctx, pools, args.serve_seconds, 2000.0, 0)
+        sweep_runs = [run_serving(L, ctx, pools, args.serve_sweep_seconds, r, 0, seed=6)
+                      for r in (1000.0, 4000.0, 8000.0, 16000.0, 32000.0)]
+        per_request = [run_serving(L, ctx, pools, args.serve_sweep_seconds, r, 1, seed=6)
+                       for r in (2000.0, 8000.0)]
+        serving = dict(main_run)
+        serving["workload"] = ("Poisson arrivals: 50% solve requests (n ~ U{2..32}, 1k-1M systems, "
+                               "log-uniform), 50% Newton updates of device-resident point sets "
+                               "(1k-500k points, 7x7/13x13 at 50/50); device-resident payloads")
+        serving["rate_sweep"] = sweep_runs
+        serving["per_request_mode"] = per_request
+        del pools
+        torch.cuda.empty_cache()
 
     # ------------------------------------------------------------- latency
     lat = {}
@@ -620,39 +744,21 @@ def main():
     # ------------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu:
-        import oracle
-        cores = min(16, os.cpu_count() or 1)
-        S = 1 << 19
-        t = time.perf_counter()
-        for n in sizes:
-            A, b = host[n]
-            oracle.gesv_batch(A[:S], b[:S], threads=cores)
-        dt = time.perf_counter() - t
-        cpu = {"value": round(len(sizes) * S / dt), "unit": "systems/s", "cores": cores,
-               "kind": "oracle",
-               "sample": f"first {S} systems of each n in {list(sizes)} (AoS; the oracle has one "
-                         f"layout), same inputs as the GPU sweep, {dt:.1f}s wall"}
-        if not args.no_newton:
-            P = 1 << 16
-            deps = newton_points(P, seed=4)
-            nt = {}
-            for kind in (7, 13):
-                t = time.perf_counter()
-                oracle.constitutive_update(oracle.Law(kind=kind), deps, threads=cores)
-                nt[f"norton{kind}_updates_per_s"] = round(P / (time.perf_counter() - t))
-            cpu["newton"] = nt
-        log(f"cpu oracle {cpu['value']} systems/s on {cores} threads")
+        cpu = cpu_oracle_baseline(host, sizes, newton=not args.no_newton)
+        log(f"cpu oracle {cpu['value']} systems/s on {cpu['cores']} threads, "
+            f"{cpu['one_core']['systems_per_s']} on one")
 
     out = {
         "metric": METRIC, "value": round(value), "unit": "systems/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "LUpp sweep: 2^20 FP64 systems for each n in {4,8,12,16,24,32}, "
-                               "A ~ N(0,1) rejected if cond2 > 1e4, b = A x_true, x_true ~ U(-1,1), "
-                               "SoA and AoS, one RHS",
-                   "batch_per_n": BATCH, "n": list(sizes), "layouts": list(layouts),
+        "config": {"workload": "LUpp sweep: 2^20 FP64 systems for each n in {8,12,16,24,32} "
+                               "(n = 4 of the same sweep reported beside it), A ~ N(0,1) rejected "
+                               "if cond2 > 1e4, b = A x_true, x_true ~ U(-1,1), SoA and AoS, one RHS",
+                   "batch_per_n": BATCH, "n": list(STEP_SIZES), "layouts": list(layouts),
                    "mode": "strict (bitwise-reproducible, no FMA, true division)"},
+        "sweep_n4_to_32": sweep_all,
         "roofline": roofline,
         "newton": newton,
         "sweep": sweep,

@@ -125,10 +125,46 @@ int lupp_check_solve_args(int n, int64_t batch, int layout, const double *A, int
  * first; no host synchronisation. Each size uses the lane count of the
  * context's ragged table (lupp_set_ragged_lanes). A system whose n is
  * outside 1..32 gets info = -1 and is not touched. flags: LUPP_KEEP_A,
- * LUPP_RAGGED_PER_SIZE. */
+ * LUPP_RAGGED_PER_SIZE.
+ * Calls on one context share its workspace: a call on a different stream
+ * than the previous one first waits (on the device) for the previous call's
+ * kernels, so calls from one host thread may use any streams. A call made
+ * while `stream` is being captured into a graph is not ordered that way:
+ * replays of such a graph must not overlap other ragged calls on the same
+ * context. */
 int lupp_batched_solve_ragged(lupp_ctx *ctx, int64_t batch, const int32_t *n,
                               const int64_t *offA, const int64_t *offB, double *A, double *b,
                               int32_t *ipiv, int32_t *info, unsigned flags, void *stream);
+
+/* Several uniform batches of different sizes in one call (Section 4.1:
+ * size-aware dispatch): group g holds groups[g].batch systems of size
+ * groups[g].n, AoS, system s at A + s*strideA (column-major, leading
+ * dimension lda), right-hand side at b + s*strideB, pivots at ipiv + s*n and
+ * info[s]. The groups are served by one launch per size class (sizes 17..32,
+ * then 1..16), kMaxGroups = 32 groups per launch, largest sizes first, each
+ * size with the lane count of the context's ragged table; every workgroup
+ * takes one work item of one group, found in the launch's argument table.
+ * No device workspace, no grouping kernels, no host synchronisation; the
+ * groups array is read during the call only (host memory). Results are
+ * bitwise those of lupp_batched_solve on each group (textbook pivoting,
+ * strict arithmetic). Groups must not overlap.
+ *   ngroups : >= 0 (0 is a no-op).
+ *   groups  : host array of ngroups descriptors: n in 1..32, batch in
+ *             0..2^31-1, and for batch > 0: non-NULL A, b, ipiv, info,
+ *             lda >= n, strideA >= lda*n, strideB >= n; otherwise -3.
+ *   flags   : 0 or LUPP_KEEP_A (-4 otherwise). */
+typedef struct {
+    int n;
+    int64_t batch;
+    double *A;
+    int64_t lda, strideA;
+    double *b;
+    int64_t strideB;
+    int32_t *ipiv;
+    int32_t *info;
+} lupp_group;
+int lupp_batched_solve_grouped(lupp_ctx *ctx, int ngroups, const lupp_group *groups,
+                               unsigned flags, void *stream);
 
 /* Lanes per system of the ragged path (Section 4.1: size-aware dispatch).
  * The ragged kernels hold, for every size n, the lane counts
@@ -318,31 +354,52 @@ void lupp_sweep_destroy(lupp_sweep *sweep);
  * Serving loop: continuous batching of solve and constitutive-update requests
  * under an HBM budget.
  *
- * The server owns a device arena of hbm_budget_bytes. A submitted request
- * waits until its footprint fits in the free arena and one of max_inflight
- * slots is free (admission in submission order; a request whose point set
- * is busy lets later requests pass). Its inputs are then copied into the
- * arena, its kernels run on one of `streams` HIP streams, so admitted
- * requests overlap on the GPU, its outputs are copied out, and its arena
- * range is released, which admits the requests queued behind it.
+ * A scheduler thread admits waiting requests in submission order while one
+ * of max_inflight slots is free and the arena (a device allocation of
+ * hbm_budget_bytes) holds their staging buffers; a request whose point set is
+ * busy lets later requests pass. Everything admitted in one scheduling pass
+ * runs together on one of `streams` HIP streams (successive passes overlap on
+ * the GPU):
+ *   LUPP_SERVE_MERGED (default): the solve requests of the pass with fewer
+ *     than 32768 systems are the groups of one grouped solve (see
+ *     lupp_batched_solve_grouped), larger ones are solved one call each with
+ *     the size-aware dispatch table, and the update requests with the same
+ *     law, tol, maxit and tangent choice share one fused-Newton launch over
+ *     their point sets;
+ *   LUPP_SERVE_PER_REQUEST: one pass and one launch per request (each solve
+ *     with lupp_batched_solve's dispatch table).
+ * A context with tile-local pivoting or a forced variant has its solves run
+ * per request in either mode, with those settings.
  *
- * Request pointers may be host or device pointers (the copy direction is
- * detected). They must stay valid until the ticket completes. Host buffers
- * should be pinned (hipHostMalloc) for the copies to overlap; pageable ones
- * work but copy synchronously.
+ * Request pointers may be host or device pointers (detected per pointer).
+ * Device data is used in place: a device A is only read (the factors are
+ * written to lu, if given), the right-hand sides are copied into a device x
+ * (unless x == b) and solved there, device outputs are written directly.
+ * Host inputs are copied into the arena and host outputs copied back from
+ * it; so are outputs given as NULL (and then dropped). The arena holds only
+ * these staging buffers. Pointers must stay valid until the ticket
+ * completes. Host buffers should be pinned (hipHostMalloc) for the copies to
+ * overlap; pageable ones work but copy synchronously.
  *
  * Integration-point state is device-resident: a point set is registered
  * once and every update request on it advances its state (committed per
  * point on convergence). Requests on the same set run in submission order.
  * Results of a request are bitwise identical whether it runs alone or among
- * others: each system or point is computed independently and identically.
+ * others, in either mode: each system or point is computed independently and
+ * identically. The server works on a context of its own holding a copy of
+ * the creating context's settings (dispatch and ragged tables, pivoting,
+ * Newton mapping) at creation.
  */
 typedef struct lupp_server lupp_server;
+
+#define LUPP_SERVE_MERGED 0
+#define LUPP_SERVE_PER_REQUEST 1
 
 typedef struct {
     int64_t hbm_budget_bytes; /* device arena; 0 = a quarter of the free memory */
     int max_inflight;         /* requests admitted at once, >= 1 */
     int streams;              /* HIP streams, 1..64 */
+    int mode;                 /* LUPP_SERVE_MERGED or LUPP_SERVE_PER_REQUEST */
 } lupp_server_config;
 
 #define LUPP_REQ_SOLVE 1
@@ -350,7 +407,8 @@ typedef struct {
 
 typedef struct {
     int kind; /* LUPP_REQ_SOLVE or LUPP_REQ_UPDATE */
-    /* LUPP_REQ_SOLVE: `batch` packed column-major systems of size n (1..32) */
+    /* LUPP_REQ_SOLVE: `batch` (1..2^31-1) packed column-major systems of size
+     * n (1..32) */
     int n;
     int64_t batch;
     const double *A; /* [batch][n*n] in */
@@ -381,6 +439,8 @@ typedef struct {
     int64_t peak_bytes, budget_bytes;
     double p50_ms, p99_ms, mean_ms, max_ms; /* submit -> completion, completed requests */
     double elapsed_s;                        /* first submit -> last completion */
+    int64_t passes;                          /* scheduling passes run */
+    int64_t launches;                        /* solve / update calls they made */
 } lupp_server_stats;
 
 /* Create a server on ctx's device (it uses a context of its own internally).

@@ -6,6 +6,7 @@
 #include <new>
 
 #include "internal.h"
+#include "serving.h"
 
 namespace lupp {
 
@@ -69,6 +70,26 @@ static LaunchFn pick(int n, const Choice &c)
     if (c.variant == LUPP_VARIANT_LANES) return lanes_launcher(n, c.lanes);
     return nullptr;
 }
+
+void ctx_copy_settings(lupp_ctx *dst, const lupp_ctx *src)
+{
+    dst->forced_variant = src->forced_variant;
+    dst->forced_lanes = src->forced_lanes;
+    dst->forced_wpb = src->forced_wpb;
+    std::memcpy(dst->table, src->table, sizeof(dst->table));
+    dst->newton_lanes[0] = src->newton_lanes[0];
+    dst->newton_lanes[1] = src->newton_lanes[1];
+    dst->tile = src->tile;
+    dst->thresh = src->thresh;
+    std::memcpy(dst->ragged_lanes, src->ragged_lanes, sizeof(dst->ragged_lanes));
+}
+
+bool ctx_textbook_dispatch(const lupp_ctx *ctx)
+{
+    return ctx->tile == 0 && ctx->forced_variant == LUPP_VARIANT_AUTO;
+}
+
+const uint8_t *ctx_ragged_lanes(const lupp_ctx *ctx) { return ctx->ragged_lanes; }
 
 }  // namespace lupp
 
@@ -235,6 +256,30 @@ int lupp_batched_solve_ragged(lupp_ctx *ctx, int64_t batch, const int32_t *n,
     const int rc = ragged_launch_impl(ctx->ragged_ws, ctx->ragged_lanes, batch, n, offA, offB, A,
                                       b, ipiv, info, (flags & LUPP_KEEP_A) == 0,
                                       (flags & LUPP_RAGGED_PER_SIZE) != 0, (hipStream_t)stream);
+    if (cur != ctx->device) hipSetDevice(cur);
+    return rc;
+}
+
+int lupp_batched_solve_grouped(lupp_ctx *ctx, int ngroups, const lupp_group *groups,
+                               unsigned flags, void *stream)
+{
+    if (ctx == nullptr) return -1;
+    if (ngroups < 0) return -2;
+    if (ngroups > 0 && groups == nullptr) return -3;
+    for (int i = 0; i < ngroups; ++i) {
+        const lupp_group &g = groups[i];
+        if (g.n < 1 || g.n > 32 || g.batch < 0 || g.batch > 0x7fffffff) return -3;
+        if (g.batch == 0) continue;
+        if (g.A == nullptr || g.b == nullptr || g.ipiv == nullptr || g.info == nullptr) return -3;
+        if (g.lda < g.n || g.strideA < g.lda * g.n || g.strideB < g.n) return -3;
+    }
+    if ((flags & ~LUPP_KEEP_A) != 0) return -4;
+    if (ngroups == 0) return 0;
+    int cur = 0;
+    hipGetDevice(&cur);
+    if (cur != ctx->device) hipSetDevice(ctx->device);
+    const int rc = grouped_enqueue(groups, ngroups, ctx->ragged_lanes, (flags & LUPP_KEEP_A) == 0,
+                                   (hipStream_t)stream);
     if (cur != ctx->device) hipSetDevice(cur);
     return rc;
 }

@@ -7,31 +7,56 @@
  * component c of point p at ptr[c*ld + p].
  */
 #include "law.h"
+#include "serving.h"
 
 namespace lupp {
 
+/* One workgroup of 256 points, the first at p0: the whole Newton loop of
+ * every point, then its stress, state (on convergence), iterations, status
+ * and optionally its tangent. */
 template <int NU, bool TAN>
-__global__ void __launch_bounds__(256) k_newton(lupp_points pts, LawK P, double tol, int maxit)
+__device__ __forceinline__ void newton_block(const lupp_points &pts, const LawK &P, double tol,
+                                             int maxit, int64_t p0)
 {
     constexpr bool kTangent = TAN;
-    const int64_t p0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x;
     const int64_t rem = pts.count - p0;
     const uint32_t nvalid = (uint32_t)(rem < (int64_t)blockDim.x ? rem : blockDim.x);
     const uint32_t tid = threadIdx.x;
     const uint32_t nb = nvalid * 8u, vo = tid * 8u;
-
-    double de[6], st[NU], y[NU], F[NU], sig[6];
+    /* The strain increment, the state at the start of the step and the
+     * unknowns live in LDS, one column of 256 doubles per component (each
+     * lane reads its own entries: no bank conflicts, no barrier), and are
+     * read at the start of every iteration: the registers stay free for the
+     * Jacobian and its factorisation (13 unknowns: 169 doubles). */
+    __shared__ double sh[(6 + 2 * NU) * 256];
+    auto DE = [&](int c) -> double & { return sh[c * 256 + tid]; };
+    auto ST = [&](int c) -> double & { return sh[(6 + c) * 256 + tid]; };
+    auto Y = [&](int c) -> double & { return sh[(6 + NU + c) * 256 + tid]; };
 #pragma unroll
-    for (int c = 0; c < 6; ++c) de[c] = buf_load_f64(make_rsrc(pts.deps + c * pts.ld + p0, nb), vo, 0);
+    for (int c = 0; c < 6; ++c) DE(c) = buf_load_f64(make_rsrc(pts.deps + c * pts.ld + p0, nb), vo, 0);
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
-        st[c] = buf_load_f64(make_rsrc(pts.state + c * pts.ld + p0, nb), vo, 0);
-        y[c] = 0.0;
+        ST(c) = buf_load_f64(make_rsrc(pts.state + c * pts.ld + p0, nb), vo, 0);
+        Y(c) = 0.0;
     }
+    auto read_inputs = [&](double (&de)[6], double (&st)[NU], double (&y)[NU])
+                           __attribute__((always_inline)) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) de[c] = DE(c);
+#pragma unroll
+        for (int c = 0; c < NU; ++c) {
+            st[c] = ST(c);
+            y[c] = Y(c);
+        }
+    };
 
     int status = 1, it = 0;
     for (;; ++it) {
+        /* keeps the reads inside the loop (no hoisting into registers) */
+        asm volatile("" ::: "memory");
+        double de[6], st[NU], y[NU], F[NU], sig[6];
         double J[NU][NU];
+        read_inputs(de, st, y);
         law_assemble<NU>(P, de, st, y, F, J, sig);
         bool finite = true;
         double nrm = 0.0;
@@ -47,11 +72,15 @@ __global__ void __launch_bounds__(256) k_newton(lupp_points pts, LawK P, double 
         int piv[NU];
 #pragma unroll
         for (int i = 0; i < NU; ++i) dx[i] = -F[i];
-        if (thread_getrf_solve<NU, false>(J, dx, piv) != 0) { status = 2; break; }
+        if (thread_getrf_solve<NU, false, false, false, true>(J, dx, piv) != 0) { status = 2; break; }
 #pragma unroll
-        for (int i = 0; i < NU; ++i) y[i] = y[i] + dx[i];
+        for (int i = 0; i < NU; ++i) Y(i) = Y(i) + dx[i];
     }
 
+    asm volatile("" ::: "memory");
+    double de[6], st[NU], y[NU], sig[6];
+    read_inputs(de, st, y);
+    law_stress<NU>(P, st, y, sig); /* the stress of the returned iterate */
 #pragma unroll
     for (int c = 0; c < 6; ++c) buf_store_f64(make_rsrc(pts.sig + c * pts.ld + p0, nb), vo, 0, sig[c]);
     const uint32_t vs = status == 0 ? vo : kOutOfRange;
@@ -67,6 +96,41 @@ __global__ void __launch_bounds__(256) k_newton(lupp_points pts, LawK P, double 
             else newton_tangent13(P, de, st, y, pts, p0, nb, vo);
         }
     }
+}
+
+/* Occupancy: 7 unknowns fit 3 waves per SIMD without scratch (146 VGPRs; 4
+ * waves would spill 52 bytes per lane); 13 unknowns take the whole register
+ * file of one wave (VGPRs and AGPRs) and no scratch. */
+template <int NU>
+constexpr int newton_waves_per_eu() { return NU == 7 ? 3 : 1; }
+
+template <int NU, bool TAN>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(newton_waves_per_eu<NU>())))
+    k_newton(lupp_points pts, LawK P, double tol, int maxit)
+{
+    newton_block<NU, TAN>(pts, P, tol, maxit, (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x);
+}
+
+/* Several point sets of one law in one launch (the serving loop's merged
+ * updates): workgroup w takes block w of the concatenated sets, and the
+ * set table in the kernel arguments (scalar loads) gives its set. */
+constexpr int kMaxNewtonGroups = 24;
+struct NewtonGroups {
+    int32_t nsets;
+    int32_t block0[kMaxNewtonGroups]; /* first workgroup of each set, ascending */
+    lupp_points pts[kMaxNewtonGroups];
+};
+
+template <int NU, bool TAN>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(newton_waves_per_eu<NU>())))
+    k_newton_grouped(NewtonGroups g, LawK P, double tol, int maxit)
+{
+    const int b = (int)xcd_block(blockIdx.x, gridDim.x);
+    int gi = 0;
+    for (int k = 1; k < g.nsets; ++k)
+        if (b >= g.block0[k]) gi = k;
+    gi = __builtin_amdgcn_readfirstlane(gi);
+    newton_block<NU, TAN>(g.pts[gi], P, tol, maxit, (int64_t)(b - g.block0[gi]) * blockDim.x);
 }
 
 /* Lanes-per-point form of the same fused update (Section 3.2.1 and Section
@@ -206,6 +270,36 @@ int constitutive_launch(const lupp_points *pts, const lupp_law *law, double tol,
         else hipLaunchKernelGGL((k_newton<13, false>), g, b, 0, stream, *pts, P, tol, maxit);
     }
     return hip_err(hipGetLastError());
+}
+
+int constitutive_launch_grouped(const lupp_points *sets, int nsets, const lupp_law *law,
+                                double tol, int maxit, hipStream_t stream)
+{
+    const LawK P = law_constants(law);
+    const bool tan = nsets > 0 && sets[0].tangent != nullptr;
+    for (int i0 = 0; i0 < nsets; i0 += kMaxNewtonGroups) {
+        NewtonGroups g{};
+        int64_t blocks = 0;
+        for (int i = i0; i < nsets && g.nsets < kMaxNewtonGroups; ++i) {
+            if (sets[i].count <= 0) continue;
+            g.block0[g.nsets] = (int32_t)blocks;
+            g.pts[g.nsets] = sets[i];
+            ++g.nsets;
+            blocks += (sets[i].count + 255) / 256;
+        }
+        if (g.nsets == 0) continue;
+        const dim3 grid((unsigned)blocks), blk(256);
+        if (law->kind == LUPP_LAW_NORTON7) {
+            if (tan) hipLaunchKernelGGL((k_newton_grouped<7, true>), grid, blk, 0, stream, g, P, tol, maxit);
+            else hipLaunchKernelGGL((k_newton_grouped<7, false>), grid, blk, 0, stream, g, P, tol, maxit);
+        } else {
+            if (tan) hipLaunchKernelGGL((k_newton_grouped<13, true>), grid, blk, 0, stream, g, P, tol, maxit);
+            else hipLaunchKernelGGL((k_newton_grouped<13, false>), grid, blk, 0, stream, g, P, tol, maxit);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_err(e);
+    }
+    return 0;
 }
 
 const void *constitutive_kernel_symbol(int kind, bool tangent)

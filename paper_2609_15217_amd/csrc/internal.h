@@ -63,6 +63,13 @@ const void *constitutive_kernel_symbol(int kind, bool tangent);
 
 /* Ragged batch (ragged.hip): device workspace owned by a context. */
 struct RaggedWs;
+struct RaggedPlan;
+/* Enqueue the grouping kernels and the solve of a ragged batch on st, with
+ * the caller's workspace: plan (one RaggedPlan) and sorted (batch int32
+ * system indices). Allocates nothing. */
+int ragged_enqueue(RaggedPlan *plan, int32_t *sorted, const uint8_t *lanes, int64_t batch,
+                   const int32_t *n, const int64_t *offA, const int64_t *offB, double *A, double *b,
+                   int32_t *ipiv, int32_t *info, bool factors, bool per_size, hipStream_t st);
 RaggedWs *ragged_ws_create();
 void ragged_ws_destroy(RaggedWs *ws);
 /* lanes[n] (n = 1..32): lanes per system used for size n (ragged_lanes_ok). */
@@ -75,6 +82,9 @@ int ragged_launch_impl(RaggedWs *ws, const uint8_t *lanes, int64_t batch, const 
  * fastest (median of reps timed runs after one warm-up). */
 int ragged_autotune_impl(RaggedWs *ws, uint8_t *lanes, int n, int64_t batch, const double *A,
                          const double *b, int reps, int *best, float *best_ms, hipStream_t st);
+/* Grouped batches (grouped.hip): enqueue the launches of validated groups. */
+int grouped_enqueue(const lupp_group *groups, int ngroups, const uint8_t *lanes, bool factors,
+                    hipStream_t st);
 /* Measured default lanes per size for the ragged path (compiled in from
  * the autotuner's table); false if the table has no entry for n. */
 bool tuned_ragged(int n, int *lanes);

@@ -45,7 +45,11 @@ struct RaggedArgs {
     int factors;
     int32_t *sorted;
     RaggedPlan *plan;
-    uint8_t lanes[33]; /* lanes per system for each size (ragged_lanes_ok) */
+    /* lanes per system for each size (ragged_lanes_ok). Words, not bytes:
+     * 4-byte-aligned kernel arguments are read by scalar loads, where a byte
+     * array is loaded into vector registers (and, in the persistent
+     * kernels, spilled to scratch memory) */
+    int32_t lanes[33];
 };
 
 /* systems one workgroup solves at once with T lanes per system */
@@ -64,46 +68,65 @@ __host__ __device__ constexpr int ragged_per_item(int T)
     return kRaggedRounds * ragged_per_round(T);
 }
 
-template <int N, int T>
-__device__ __forceinline__ void ragged_item(const RaggedArgs &a, int first, int cnt)
+/* Where the j-th system of a work item lives: matrix (column-major, leading
+ * dimension lda()), right-hand side, pivots and info. */
+struct SysPtrs {
+    double *A, *b;
+    int32_t *ipiv, *info;
+};
+
+/* Ragged batches: the item's systems are entries of the sorted index list,
+ * each at its own offsets, packed (lda = n). */
+template <int N>
+struct RaggedLoc {
+    const RaggedArgs &a;
+    const int32_t *idx;
+    __device__ __forceinline__ SysPtrs sys(int j) const
+    {
+        const int64_t s = idx[j];
+        return {a.A + a.offA[s], a.b + a.offB[s], a.ipiv + a.offB[s], a.info + s};
+    }
+    __device__ __forceinline__ int64_t lda() const { return N; }
+};
+
+/* Solve the cnt (>= 1) systems of one work item with the whole workgroup, T
+ * lanes per system (T == 1: one thread per system). Threads or segments
+ * without a system point at system 0, load zeros and store nothing. */
+template <int N, int T, typename Loc>
+__device__ __forceinline__ void solve_item(const Loc &loc, int cnt, int factors)
 {
-    const int32_t *idx = a.sorted + a.plan->bin_start[N] + first;
+    const int64_t lda = loc.lda();
     if constexpr (T == 1) {
         const int i = threadIdx.x;
         const bool act = i < cnt;
-        const int64_t s = act ? idx[i] : 0;
-        const double *pA = a.A + (act ? a.offA[s] : 0);
-        const double *pB = a.b + (act ? a.offB[s] : 0);
+        const SysPtrs p = loc.sys(act ? i : 0); /* cnt >= 1: system 0 exists */
         double m[N][N], x[N];
         int piv[N];
         static_for<0, N>([&](auto jc) __attribute__((always_inline)) {
             constexpr int j = decltype(jc)::value;
             static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
                 constexpr int ii = decltype(ic)::value;
-                m[j][ii] = act ? pA[ii + j * N] : 0.0;
+                m[j][ii] = act ? p.A[ii + j * lda] : 0.0;
             });
-            x[j] = act ? pB[j] : 0.0;
+            x[j] = act ? p.b[j] : 0.0;
         });
         const int inf = thread_getrf_solve<N, true>(m, x, piv);
         if (act) {
-            double *wA = a.A + a.offA[s];
-            double *wB = a.b + a.offB[s];
-            int32_t *wP = a.ipiv + a.offB[s];
-            if (a.factors) {
+            if (factors) {
                 static_for<0, N>([&](auto jc) __attribute__((always_inline)) {
                     constexpr int j = decltype(jc)::value;
                     static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
                         constexpr int ii = decltype(ic)::value;
-                        wA[ii + j * N] = m[j][ii];
+                        p.A[ii + j * lda] = m[j][ii];
                     });
                 });
             }
             static_for<0, N>([&](auto kc) __attribute__((always_inline)) {
                 constexpr int k = decltype(kc)::value;
-                wP[k] = piv[k];
-                if (inf == 0) wB[k] = x[k];
+                p.ipiv[k] = piv[k];
+                if (inf == 0) p.b[k] = x[k];
             });
-            a.info[s] = inf;
+            *p.info = inf;
         }
     } else {
         constexpr int K = lanes_shape<N, T>::K;
@@ -113,9 +136,7 @@ __device__ __forceinline__ void ragged_item(const RaggedArgs &a, int first, int 
         const int wave = threadIdx.x >> 6;
         const int j0 = wave * SPW + g;
         const bool act = j0 < cnt;
-        const int64_t s = act ? idx[j0] : 0;
-        const double *pA = a.A + (act ? a.offA[s] : 0);
-        const double *pB = a.b + (act ? a.offB[s] : 0);
+        const SysPtrs p = loc.sys(act ? j0 : 0); /* cnt >= 1: system 0 exists */
         double m[K][N], x[K];
         int pos[K];
         static_for<0, K>([&](auto sc) __attribute__((always_inline)) {
@@ -125,9 +146,9 @@ __device__ __forceinline__ void ragged_item(const RaggedArgs &a, int first, int 
             pos[sl] = r < N ? r : -1;
             static_for<0, N>([&](auto jc) __attribute__((always_inline)) {
                 constexpr int j = decltype(jc)::value;
-                m[sl][j] = ok ? pA[r + j * N] : 0.0;
+                m[sl][j] = ok ? p.A[r + j * lda] : 0.0;
             });
-            x[sl] = ok ? pB[r] : 0.0;
+            x[sl] = ok ? p.b[r] : 0.0;
         });
         constexpr int KP = (N + T - 1) / T;
         int pv[KP];
@@ -143,28 +164,32 @@ __device__ __forceinline__ void ragged_item(const RaggedArgs &a, int first, int 
             });
         });
         if (act) {
-            double *wA = a.A + a.offA[s];
-            double *wB = a.b + a.offB[s];
-            int32_t *wP = a.ipiv + a.offB[s];
             static_for<0, K>([&](auto sc) __attribute__((always_inline)) {
                 constexpr int sl = decltype(sc)::value;
                 if (pos[sl] >= 0) {
-                    if (a.factors) {
+                    if (factors) {
                         static_for<0, N>([&](auto jc) __attribute__((always_inline)) {
                             constexpr int j = decltype(jc)::value;
-                            wA[pos[sl] + j * N] = m[sl][j];
+                            p.A[pos[sl] + j * lda] = m[sl][j];
                         });
                     }
-                    if (inf == 0) wB[pos[sl]] = x[sl];
+                    if (inf == 0) p.b[pos[sl]] = x[sl];
                 }
             });
             static_for<0, KP>([&](auto sc) __attribute__((always_inline)) {
                 constexpr int c = decltype(sc)::value;
-                if (t + c * T < N) wP[t + c * T] = pv[c];
+                if (t + c * T < N) p.ipiv[t + c * T] = pv[c];
             });
-            if (t == 0) a.info[s] = inf;
+            if (t == 0) *p.info = inf;
         }
     }
+}
+
+template <int N, int T>
+__device__ __forceinline__ void ragged_item(const RaggedArgs &a, int first, int cnt)
+{
+    const RaggedLoc<N> loc{a, a.sorted + a.plan->bin_start[N] + first};
+    solve_item<N, T>(loc, cnt, a.factors);
 }
 
 template <int N, int T>
@@ -252,6 +277,101 @@ __device__ __forceinline__ void ragged_persistent_loop(const RaggedArgs &a, int3
         ragged_dispatch<LO>(a, n, it, std::make_integer_sequence<int, HI - LO + 1>{});
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Grouped batches: up to kMaxGroups uniform batches, each with its own size,  */
+/* pointers and strides (AoS), solved by one launch per size class. The host   */
+/* knows every group's size, so no grouping kernels and no work counter are   */
+/* needed: workgroup w takes work item w, and the group table (kernel          */
+/* arguments, read with scalar loads) gives its group.                         */
+/* ------------------------------------------------------------------------ */
+constexpr int kMaxGroups = 32;
+
+struct GroupDesc {
+    double *A, *b;
+    int32_t *ipiv, *info;
+    int64_t lda, sA, sB, batch;
+    int32_t n, lanes;
+    int32_t item0;   /* first work item of the group in its launch */
+    int32_t factors; /* write the factors back (else A is only read) */
+};
+
+struct GroupedArgs {
+    int32_t ngroups, pad;
+    GroupDesc g[kMaxGroups]; /* ascending item0 */
+};
+
+/* System s of a group: matrix at A + s*sA (leading dimension lda), right-hand
+ * side at b + s*sB, pivots at ipiv + s*n, info[s]. */
+template <int N>
+struct GroupLoc {
+    const GroupDesc &g;
+    int64_t first;
+    __device__ __forceinline__ SysPtrs sys(int j) const
+    {
+        const int64_t s = first + j;
+        return {g.A + s * g.sA, g.b + s * g.sB, g.ipiv + s * N, g.info + s};
+    }
+    __device__ __forceinline__ int64_t lda() const { return g.lda; }
+};
+
+/* systems of one grouped work item: one round of the workgroup */
+__host__ __device__ constexpr int grouped_per_item(int T) { return ragged_per_round(T); }
+
+template <int N, int T>
+__device__ __forceinline__ bool grouped_try_lanes(const GroupDesc &g, int lanes, int local,
+                                                  int factors)
+{
+    if constexpr (ragged_lanes_ok(N, T)) {
+        if (lanes == T) {
+            const int64_t first = (int64_t)local * grouped_per_item(T);
+            const int64_t rest = g.batch - first;
+            const int cnt = (int)(rest < grouped_per_item(T) ? rest : grouped_per_item(T));
+            solve_item<N, T>(GroupLoc<N>{g, first}, cnt, factors);
+            return true;
+        }
+    }
+    return false;
+}
+
+template <int N>
+__device__ __forceinline__ bool grouped_try(const GroupDesc &g, int n, int local, int factors)
+{
+    if (n != N) return false;
+    const int lanes = __builtin_amdgcn_readfirstlane(g.lanes);
+    (void)(grouped_try_lanes<N, 1>(g, lanes, local, factors) ||
+           grouped_try_lanes<N, 2>(g, lanes, local, factors) ||
+           grouped_try_lanes<N, 4>(g, lanes, local, factors) ||
+           grouped_try_lanes<N, 8>(g, lanes, local, factors) ||
+           grouped_try_lanes<N, 16>(g, lanes, local, factors));
+    return true;
+}
+
+template <int LO, int... Ns>
+__device__ __forceinline__ void grouped_dispatch(const GroupDesc &g, int n, int local, int factors,
+                                                 std::integer_sequence<int, Ns...>)
+{
+    (void)(grouped_try<LO + Ns>(g, n, local, factors) || ...);
+}
+
+/* Work item `it` of a grouped launch over sizes LO..HI (all threads of the
+ * workgroup): find its group (uniform), then solve its systems. */
+template <int LO, int HI>
+__device__ __forceinline__ void grouped_run(const GroupedArgs &a, int it)
+{
+    int gi = 0;
+    for (int k = 1; k < a.ngroups; ++k)
+        if (it >= a.g[k].item0) gi = k;
+    gi = __builtin_amdgcn_readfirstlane(gi);
+    const GroupDesc &g = a.g[gi];
+    grouped_dispatch<LO>(g, __builtin_amdgcn_readfirstlane(g.n), it - g.item0, g.factors,
+                         std::make_integer_sequence<int, HI - LO + 1>{});
+}
+
+/* The grouped kernels (grouped_large.hip, grouped_small.hip): one workgroup
+ * per work item. */
+hipError_t grouped_large_launch(const GroupedArgs &a, unsigned items, hipStream_t st);
+hipError_t grouped_small_launch(const GroupedArgs &a, unsigned items, hipStream_t st);
 
 /* The two persistent kernels (ragged_large.hip, ragged_small.hip: separate
  * translation units, compiled in parallel): `grid` workgroups each. */

@@ -21,7 +21,29 @@ namespace lupp {
 
 struct LawK {
     double lam, two_mu, dtA, m, c23, D;
+    int mi; /* m when it is an integer in 1..64 (powers by multiplication), else 0 */
 };
+
+/* seq^(m-1) and seq^m for seq > 0. An integer exponent (the benchmark's
+ * m = 5) takes repeated squaring: a handful of multiplies instead of two
+ * pow calls (each a log/exp sequence of ~100 instructions), and within a
+ * few ulps of pow, as pow itself is of the correctly rounded power. The loop
+ * count is uniform across the wave. */
+__device__ __forceinline__ void law_powers(const LawK &P, double seq, double &pm1, double &pm)
+{
+    if (P.mi > 0) {
+        double r = 1.0, b = seq;
+        for (int e = P.mi - 1; e != 0; e >>= 1) {
+            if (e & 1) r = r * b;
+            b = b * b;
+        }
+        pm1 = r;
+        pm = r * seq;
+    } else {
+        pm1 = pow(seq, P.m - 1.0);
+        pm = pow(seq, P.m);
+    }
+}
 
 /* What the residual and every Jacobian row need at the unknowns y: stress,
  * flow direction N, back-strain alpha, the scalars of the Jacobian blocks,
@@ -32,18 +54,28 @@ struct LawC {
     double inv, dp, gd, dp2mu, cdp, nmean;
 };
 
+/* Stress at the unknowns y: sig = lambda tr(eel) 1 + 2 mu eel, eel = eel_t +
+ * d_eel (the expression law_common uses, so the result is the same bits). */
+template <int NU>
+__device__ __forceinline__ void law_stress(const LawK &P, const double (&st)[NU],
+                                           const double (&y)[NU], double (&sig)[6])
+{
+    double e[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) e[i] = st[i] + y[i];
+    const double tr = e[0] + e[1] + e[2];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) sig[i] = P.two_mu * e[i] + (i < 3 ? P.lam * tr : 0.0);
+}
+
 template <int NU>
 __device__ __forceinline__ void law_common(const LawK &P, const double (&de)[6],
                                            const double (&st)[NU], const double (&y)[NU],
                                            LawC<NU> &C)
 {
     constexpr bool af = (NU == 13);
-    double e[6], xi[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) e[i] = st[i] + y[i];
-    const double tr = e[0] + e[1] + e[2];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) C.sig[i] = P.two_mu * e[i] + (i < 3 ? P.lam * tr : 0.0);
+    double xi[6];
+    law_stress<NU>(P, st, y, C.sig);
     const double mean = (C.sig[0] + C.sig[1] + C.sig[2]) / 3.0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
@@ -65,10 +97,11 @@ __device__ __forceinline__ void law_common(const LawK &P, const double (&de)[6],
     for (int i = 0; i < 6; ++i) C.Nv[i] = pl ? 1.5 * xi[i] / seq : 0.0;
 
     const double dp = y[6];
-    const double sm1 = pl ? pow(seq, P.m - 1.0) : 0.0;
+    double sm1 = 0.0, sm = 0.0;
+    if (pl) law_powers(P, seq, sm1, sm);
 #pragma unroll
     for (int i = 0; i < 6; ++i) C.F[i] = y[i] + dp * C.Nv[i] - de[i];
-    C.F[6] = dp - P.dtA * (pl ? pow(seq, P.m) : 0.0);
+    C.F[6] = dp - P.dtA * sm;
     if constexpr (af) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) C.F[7 + i] = y[7 + i] - dp * C.Nv[i] + P.D * dp * C.al[i];
@@ -228,7 +261,7 @@ __device__ __forceinline__ void newton_tangent7(const LawK &P, const double (&de
     law_assemble<7>(P, de, st, y, Fc, J, sc);
 #pragma unroll
     for (int i = 0; i < 7; ++i) z[i] = 0.0;
-    const bool sing = thread_getrf_solve<7, true>(J, z, piv) != 0;
+    const bool sing = thread_getrf_solve<7, true, false, false, true>(J, z, piv) != 0;
     thread_ipiv_to_perm<7>(piv, perm);
 #pragma unroll 1
     for (int c = 0; c < 6; ++c) {
@@ -242,9 +275,11 @@ __device__ __forceinline__ void newton_tangent7(const LawK &P, const double (&de
  * registers together, so each column re-assembles J and runs the fused
  * factor-and-solve on e_c. Every column sees the same factorization and the
  * same operation sequence, so the result is bitwise that of the factor-once
- * form. Not inlined: it gets its own register budget instead of adding to
- * the Newton loop's. */
-static __device__ __attribute__((noinline)) void newton_tangent13(const LawK &P, const double (&de)[6],
+ * form. Inlined: after the loop the caller holds nothing but the loop's
+ * inputs (kept in LDS by the fused kernel), so it fits the loop's register
+ * budget without scratch; a call boundary would force its array arguments
+ * into scratch memory. */
+static __device__ __forceinline__ void newton_tangent13(const LawK &P, const double (&de)[6],
                                                            const double (&st)[13],
                                                            const double (&y)[13],
                                                            const lupp_points &pts, int64_t p0,
@@ -257,7 +292,7 @@ static __device__ __attribute__((noinline)) void newton_tangent13(const LawK &P,
         law_assemble<13>(P, de, st, y, Fc, J, sc);
 #pragma unroll
         for (int i = 0; i < 13; ++i) x[i] = (i == c) ? 1.0 : 0.0;
-        const bool sing = thread_getrf_solve<13, false>(J, x, piv) != 0;
+        const bool sing = thread_getrf_solve<13, false, false, false, true>(J, x, piv) != 0;
         tangent_store_col<13>(P, pts, p0, nb, vo, c, x, sing);
     }
 }
@@ -269,6 +304,7 @@ static inline LawK law_constants(const lupp_law *law)
     P.two_mu = law->E / (1.0 + law->nu);
     P.dtA = law->dt * law->A;
     P.m = law->m;
+    P.mi = (law->m >= 1.0 && law->m <= 64.0 && law->m == (double)(int)law->m) ? (int)law->m : 0;
     P.c23 = law->kind == LUPP_LAW_NORTON_AF13 ? 2.0 / 3.0 * law->C : 0.0;
     P.D = law->kind == LUPP_LAW_NORTON_AF13 ? law->D : 0.0;
     return P;

@@ -99,10 +99,18 @@ __global__ void __launch_bounds__(256) k_ragged_scatter(RaggedArgs a)
 
 hipError_t ragged_one_launch(int n, const RaggedArgs &a, int items, hipStream_t st);
 
+/* Workspace of the allocating entry point. Calls on one context may come on
+ * different streams: `done` is recorded after each call's last kernel, and
+ * the next call on another stream waits for it before its grouping kernels
+ * reset the plan and rewrite `sorted` (which the earlier call's persistent
+ * kernels may still be reading). */
 struct RaggedWs {
     RaggedPlan *plan = nullptr;
     int32_t *sorted = nullptr;
     int64_t cap = 0;
+    hipEvent_t done = nullptr;
+    hipStream_t last = nullptr;
+    bool used = false;
 };
 
 RaggedWs *ragged_ws_create() { return new RaggedWs; }
@@ -110,39 +118,25 @@ RaggedWs *ragged_ws_create() { return new RaggedWs; }
 void ragged_ws_destroy(RaggedWs *ws)
 {
     if (ws == nullptr) return;
+    if (ws->done) {
+        hipEventSynchronize(ws->done);
+        hipEventDestroy(ws->done);
+    }
     hipFree(ws->sorted);
     hipFree(ws->plan);
     delete ws;
 }
 
-int ragged_launch_impl(RaggedWs *ws, const uint8_t *lanes, int64_t batch, const int32_t *n,
-                       const int64_t *offA, const int64_t *offB, double *A, double *b,
-                       int32_t *ipiv, int32_t *info, bool factors, bool per_size, hipStream_t st)
+int ragged_enqueue(RaggedPlan *plan, int32_t *sorted, const uint8_t *lanes, int64_t batch,
+                   const int32_t *n, const int64_t *offA, const int64_t *offB, double *A, double *b,
+                   int32_t *ipiv, int32_t *info, bool factors, bool per_size, hipStream_t st)
 {
-    if (batch > 0x7fffffff) return LUPP_E_UNSUPPORTED;
-    if (ws->cap < batch) {
-        if (ws->sorted) {
-            hipError_t e = hipStreamSynchronize(st);
-            if (e != hipSuccess) return hip_err(e);
-            hipFree(ws->sorted);
-            ws->sorted = nullptr;
-            ws->cap = 0;
-        }
-        const int64_t cap = batch < 65536 ? 65536 : batch;
-        hipError_t e = hipMalloc(&ws->sorted, (size_t)cap * sizeof(int32_t));
-        if (e != hipSuccess) return e == hipErrorOutOfMemory ? LUPP_E_NOMEM : hip_err(e);
-        ws->cap = cap;
-    }
-    if (ws->plan == nullptr) {
-        hipError_t e = hipMalloc(&ws->plan, sizeof(RaggedPlan));
-        if (e != hipSuccess) return hip_err(e);
-    }
-    RaggedArgs a{batch, n, offA, offB, A, b, ipiv, info, factors ? 1 : 0, ws->sorted, ws->plan, {}};
+    RaggedArgs a{batch, n, offA, offB, A, b, ipiv, info, factors ? 1 : 0, sorted, plan, {}};
     for (int m = 0; m <= 32; ++m) a.lanes[m] = m >= 1 ? lanes[m] : 1;
     /* grouping grid: at most 1024 workgroups of 256 threads, each a chunk */
     const int64_t full = (batch + 255) / 256;
     const unsigned blocks = (unsigned)(full < 1024 ? full : 1024);
-    hipLaunchKernelGGL(k_ragged_zero, dim3(1), dim3(64), 0, st, ws->plan);
+    hipLaunchKernelGGL(k_ragged_zero, dim3(1), dim3(64), 0, st, plan);
     hipLaunchKernelGGL(k_ragged_hist, dim3(blocks), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_ragged_plan, dim3(1), dim3(64), 0, st, a);
     hipLaunchKernelGGL(k_ragged_scatter, dim3(blocks), dim3(256), 0, st, a);
@@ -153,14 +147,15 @@ int ragged_launch_impl(RaggedWs *ws, const uint8_t *lanes, int64_t batch, const 
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         /* as many workgroups as stay resident: a CU holds 4 SIMDs x (waves per
-         * SIMD) waves, 4 waves per workgroup */
+         * SIMD) waves, 4 waves per workgroup (large: 2 waves per SIMD, small:
+         * 3) */
         e = ragged_large_launch(a, (unsigned)(cus * 2), st);
-        if (e == hipSuccess) e = ragged_small_launch(a, (unsigned)(cus * 4), st);
+        if (e == hipSuccess) e = ragged_small_launch(a, (unsigned)(cus * 3), st);
         return hip_err(e);
     }
     /* one launch per size: the host reads the plan (a synchronisation) */
     RaggedPlan h;
-    e = hipMemcpyAsync(&h, ws->plan, sizeof(h), hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(&h, plan, sizeof(h), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_err(e);
     for (int m = 32; m >= 1; --m) {
@@ -170,6 +165,53 @@ int ragged_launch_impl(RaggedWs *ws, const uint8_t *lanes, int64_t batch, const 
         if (e != hipSuccess) return hip_err(e);
     }
     return 0;
+}
+
+int ragged_launch_impl(RaggedWs *ws, const uint8_t *lanes, int64_t batch, const int32_t *n,
+                       const int64_t *offA, const int64_t *offB, double *A, double *b,
+                       int32_t *ipiv, int32_t *info, bool factors, bool per_size, hipStream_t st)
+{
+    if (batch > 0x7fffffff) return LUPP_E_UNSUPPORTED;
+    hipError_t e = hipSuccess;
+    if (ws->done == nullptr) {
+        e = hipEventCreateWithFlags(&ws->done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_err(e);
+    }
+    if (ws->cap < batch) {
+        if (ws->sorted) {
+            /* the previous call, on whatever stream, must be done with it */
+            e = hipEventSynchronize(ws->done);
+            if (e != hipSuccess) return hip_err(e);
+            hipFree(ws->sorted);
+            ws->sorted = nullptr;
+            ws->cap = 0;
+        }
+        const int64_t cap = batch < 65536 ? 65536 : batch;
+        e = hipMalloc(&ws->sorted, (size_t)cap * sizeof(int32_t));
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? LUPP_E_NOMEM : hip_err(e);
+        ws->cap = cap;
+    }
+    if (ws->plan == nullptr) {
+        e = hipMalloc(&ws->plan, sizeof(RaggedPlan));
+        if (e != hipSuccess) return hip_err(e);
+    }
+    /* a call being captured into a graph is ordered by the graph, not by
+     * the eager event chain */
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return hip_err(e);
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    if (!capturing && ws->used && ws->last != st) {
+        e = hipStreamWaitEvent(st, ws->done, 0);
+        if (e != hipSuccess) return hip_err(e);
+    }
+    const int rc = ragged_enqueue(ws->plan, ws->sorted, lanes, batch, n, offA, offB, A, b, ipiv,
+                                  info, factors, per_size, st);
+    if (capturing) return rc;
+    e = hipEventRecord(ws->done, st);
+    ws->last = st;
+    ws->used = true;
+    return rc != 0 ? rc : hip_err(e);
 }
 
 /* offsets of a packed single-size batch: system s at s*n*n (matrix) and s*n

@@ -42,6 +42,12 @@ class lupp_law(ctypes.Structure):
                 ("D", ctypes.c_double), ("dt", ctypes.c_double)]
 
 
+class lupp_group(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("batch", ctypes.c_int64), ("A", ctypes.c_void_p),
+                ("lda", ctypes.c_int64), ("strideA", ctypes.c_int64), ("b", ctypes.c_void_p),
+                ("strideB", ctypes.c_int64), ("ipiv", ctypes.c_void_p), ("info", ctypes.c_void_p)]
+
+
 class lupp_points(ctypes.Structure):
     _fields_ = [("count", _i64), ("ld", _i64), ("deps", _P), ("state", _P), ("sig", _P),
                 ("iters", _P), ("status", _P), ("tangent", _P)]
@@ -67,6 +73,8 @@ _lupp_batched_solve = _sig("lupp_batched_solve", ctypes.c_int,
                             ctypes.c_uint, _P])
 _lupp_batched_solve_ragged = _sig("lupp_batched_solve_ragged", ctypes.c_int,
                                   [_P, _i64, _P, _P, _P, _P, _P, _P, _P, ctypes.c_uint, _P])
+_lupp_batched_solve_grouped = _sig("lupp_batched_solve_grouped", ctypes.c_int,
+                                   [_P, ctypes.c_int, ctypes.POINTER(lupp_group), ctypes.c_uint, _P])
 _lupp_force_variant = _sig("lupp_force_variant", ctypes.c_int,
                            [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int])
 _lupp_set_dispatch = _sig("lupp_set_dispatch", ctypes.c_int,
@@ -98,7 +106,8 @@ _lupp_check_solve_args = _sig("lupp_check_solve_args", ctypes.c_int,
                                ctypes.c_uint])
 
 class lupp_server_config(ctypes.Structure):
-    _fields_ = [("hbm_budget_bytes", _i64), ("max_inflight", ctypes.c_int), ("streams", ctypes.c_int)]
+    _fields_ = [("hbm_budget_bytes", _i64), ("max_inflight", ctypes.c_int), ("streams", ctypes.c_int),
+                ("mode", ctypes.c_int)]
 
 
 class lupp_request(ctypes.Structure):
@@ -114,7 +123,7 @@ class lupp_server_stats(ctypes.Structure):
                 ("queued", _i64), ("inflight", ctypes.c_int), ("peak_inflight", ctypes.c_int),
                 ("peak_bytes", _i64), ("budget_bytes", _i64), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
-                ("elapsed_s", ctypes.c_double)]
+                ("elapsed_s", ctypes.c_double), ("passes", _i64), ("launches", _i64)]
 
 
 _lupp_get_device = _sig("lupp_get_device", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)])
@@ -141,7 +150,7 @@ EXPORTED = ["lupp_create", "lupp_destroy", "lupp_batched_solve", "lupp_batched_s
             "lupp_sweep_destroy", "constitutive_update_batched", "lupp_set_newton_variant",
             "lupp_get_newton_variant", "lupp_set_pivoting", "lupp_get_pivoting",
             "lupp_ragged_lanes_supported", "lupp_set_ragged_lanes", "lupp_get_ragged_lanes",
-            "lupp_autotune_ragged"]
+            "lupp_autotune_ragged", "lupp_batched_solve_grouped"]
 
 
 class LuppError(RuntimeError):
@@ -221,6 +230,22 @@ def lupp_batched_solve_ragged(ctx: Context, batch: int, n, offA, offB, A, b, ipi
                               flags: int = 0, stream=None) -> int:
     return _lupp_batched_solve_ragged(ctx.handle, batch, _ptr(n), _ptr(offA), _ptr(offB), _ptr(A),
                                       _ptr(b), _ptr(ipiv), _ptr(info), flags, _stream(stream))
+
+
+def group(n: int, batch: int, A, b, ipiv, info, lda: int | None = None,
+          strideA: int | None = None, strideB: int | None = None) -> lupp_group:
+    """One AoS group descriptor (packed strides by default)."""
+    lda = n if lda is None else lda
+    return lupp_group(n, batch, _ptr(A).value, lda, lda * n if strideA is None else strideA,
+                      _ptr(b).value, n if strideB is None else strideB, _ptr(ipiv).value,
+                      _ptr(info).value)
+
+
+def lupp_batched_solve_grouped(ctx: Context, groups, flags: int = 0, stream=None) -> int:
+    """groups: a sequence of lupp_group (or None with ngroups 0)."""
+    n = len(groups) if groups is not None else 0
+    arr = (lupp_group * max(n, 1))(*groups) if n else None
+    return _lupp_batched_solve_grouped(ctx.handle, n, arr, flags, _stream(stream))
 
 
 def lupp_check_solve_args(n: int, batch: int, layout: int, A, lda: int, strideA: int, b,
@@ -435,6 +460,7 @@ def points(deps: torch.Tensor, state: torch.Tensor, sig: torch.Tensor, iters: to
 # Serving loop
 # --------------------------------------------------------------------------
 LUPP_REQ_SOLVE, LUPP_REQ_UPDATE = 1, 2
+LUPP_SERVE_MERGED, LUPP_SERVE_PER_REQUEST = 0, 1
 
 
 def lupp_get_device(ctx: Context) -> int:
@@ -446,8 +472,9 @@ def lupp_get_device(ctx: Context) -> int:
 class Server:
     """Owns a lupp_server (device arena, streams, scheduler thread)."""
 
-    def __init__(self, ctx: Context, budget_bytes: int = 0, max_inflight: int = 8, streams: int = 4):
-        cfg = lupp_server_config(budget_bytes, max_inflight, streams)
+    def __init__(self, ctx: Context, budget_bytes: int = 0, max_inflight: int = 8, streams: int = 4,
+                 mode: int = 0):
+        cfg = lupp_server_config(budget_bytes, max_inflight, streams, mode)
         h = _P()
         _check(_lupp_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "lupp_server_create")
         self.handle = h
@@ -465,8 +492,8 @@ class Server:
 
 
 def lupp_server_create(ctx: Context, budget_bytes: int = 0, max_inflight: int = 8,
-                       streams: int = 4) -> Server:
-    return Server(ctx, budget_bytes, max_inflight, streams)
+                       streams: int = 4, mode: int = 0) -> Server:
+    return Server(ctx, budget_bytes, max_inflight, streams, mode)
 
 
 def lupp_server_destroy(server: Server):
