@@ -35,6 +35,7 @@ extern "C" {
 
 #define LUPP_E_UNSUPPORTED (-900)
 #define LUPP_E_NOMEM (-901)
+#define LUPP_E_TOO_LARGE (-902) /* beyond the allocation-free workspace */
 #define LUPP_E_HIP_BASE (-1000)
 
 /* Matrix layouts.
@@ -165,6 +166,27 @@ typedef struct {
 } lupp_group;
 int lupp_batched_solve_grouped(lupp_ctx *ctx, int ngroups, const lupp_group *groups,
                                unsigned flags, void *stream);
+
+/* Allocation-free form of lupp_batched_solve_ragged, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. It calls no hipMalloc, hipFree or
+ * allocating library routine: the grouping workspace (size plan and sorted
+ * system indices) is a fixed array of about 16 MiB in the library's device
+ * code, which each GPU holds from the first context created on it until the
+ * process ends. Arguments, results and flags as lupp_batched_solve_ragged,
+ * except:
+ *   - batch must not exceed LUPP_NOALLOC_MAX_BATCH (LUPP_E_TOO_LARGE);
+ *   - LUPP_RAGGED_PER_SIZE is refused (-10): it synchronises with the host;
+ *   - every call on a GPU shares that GPU's one workspace, whatever the
+ *     context: calls that overlap on one GPU (other streams, other threads,
+ *     replays of graphs holding such calls) race and give wrong results. The
+ *     caller serialises them. A call clears what it needs, so the contents
+ *     left by an earlier call do not matter. */
+#define LUPP_NOALLOC_MAX_BATCH 4194304
+int lupp_batched_solve_ragged_noalloc(lupp_ctx *ctx, int64_t batch, const int32_t *n,
+                                      const int64_t *offA, const int64_t *offB, double *A,
+                                      double *b, int32_t *ipiv, int32_t *info, unsigned flags,
+                                      void *stream);
 
 /* Lanes per system of the ragged path (Section 4.1: size-aware dispatch).
  * The ragged kernels hold, for every size n, the lane counts

@@ -116,6 +116,9 @@ int lupp_create(lupp_ctx **ctx, int device)
         c->ragged_lanes[n] = (uint8_t)((tuned_ragged(n, &t) && ragged_lanes_ok(n, t))
                                            ? t : ragged_default_lanes(n));
     }
+    /* set-up of the allocation-free ragged path: resolve its workspace on
+     * this device (once per device); a failure surfaces only in that call */
+    (void)noalloc_scratch_init(device);
     *ctx = c;
     return 0;
 }
@@ -280,6 +283,33 @@ int lupp_batched_solve_grouped(lupp_ctx *ctx, int ngroups, const lupp_group *gro
     if (cur != ctx->device) hipSetDevice(ctx->device);
     const int rc = grouped_enqueue(groups, ngroups, ctx->ragged_lanes, (flags & LUPP_KEEP_A) == 0,
                                    (hipStream_t)stream);
+    if (cur != ctx->device) hipSetDevice(cur);
+    return rc;
+}
+
+int lupp_batched_solve_ragged_noalloc(lupp_ctx *ctx, int64_t batch, const int32_t *n,
+                                      const int64_t *offA, const int64_t *offB, double *A,
+                                      double *b, int32_t *ipiv, int32_t *info, unsigned flags,
+                                      void *stream)
+{
+    if (ctx == nullptr) return -1;
+    if (batch < 0) return -2;
+    if (batch > 0 && n == nullptr) return -3;
+    if (batch > 0 && offA == nullptr) return -4;
+    if (batch > 0 && offB == nullptr) return -5;
+    if (batch > 0 && A == nullptr) return -6;
+    if (batch > 0 && b == nullptr) return -7;
+    if (batch > 0 && ipiv == nullptr) return -8;
+    if (batch > 0 && info == nullptr) return -9;
+    if ((flags & ~LUPP_KEEP_A) != 0) return -10;
+    if (batch > LUPP_NOALLOC_MAX_BATCH) return LUPP_E_TOO_LARGE;
+    if (batch == 0) return 0;
+    int cur = 0;
+    hipGetDevice(&cur);
+    if (cur != ctx->device) hipSetDevice(ctx->device);
+    const int rc = noalloc_ragged_enqueue(ctx->device, ctx->ragged_lanes, batch, n, offA, offB, A,
+                                          b, ipiv, info, (flags & LUPP_KEEP_A) == 0,
+                                          (hipStream_t)stream);
     if (cur != ctx->device) hipSetDevice(cur);
     return rc;
 }
@@ -525,6 +555,8 @@ const char *lupp_error_string(int code)
     if (code == 0) return "success";
     if (code == LUPP_E_UNSUPPORTED) return "request not supported by the compiled kernels";
     if (code == LUPP_E_NOMEM) return "out of memory";
+    if (code == LUPP_E_TOO_LARGE)
+        return "batch exceeds the allocation-free workspace (LUPP_NOALLOC_MAX_BATCH systems)";
     if (code <= LUPP_E_HIP_BASE) {
         std::snprintf(buf, sizeof(buf), "HIP error %d: %s", LUPP_E_HIP_BASE - code,
                       hipGetErrorString((hipError_t)(LUPP_E_HIP_BASE - code)));

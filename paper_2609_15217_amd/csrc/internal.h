@@ -85,6 +85,13 @@ int ragged_autotune_impl(RaggedWs *ws, uint8_t *lanes, int n, int64_t batch, con
 /* Grouped batches (grouped.hip): enqueue the launches of validated groups. */
 int grouped_enqueue(const lupp_group *groups, int ngroups, const uint8_t *lanes, bool factors,
                     hipStream_t st);
+/* Allocation-free ragged path (ragged_noalloc.hip): resolve the device
+ * address of the fixed workspace on `device` (once per device; lupp_create
+ * calls it), and enqueue a ragged solve that uses it. */
+int noalloc_scratch_init(int device);
+int noalloc_ragged_enqueue(int device, const uint8_t *lanes, int64_t batch, const int32_t *n,
+                           const int64_t *offA, const int64_t *offB, double *A, double *b,
+                           int32_t *ipiv, int32_t *info, bool factors, hipStream_t st);
 /* Measured default lanes per size for the ragged path (compiled in from
  * the autotuner's table); false if the table has no entry for n. */
 bool tuned_ragged(int n, int *lanes);

@@ -30,7 +30,8 @@ LUPP_FMA = 4
 LUPP_RAGGED_PER_SIZE = 2
 LUPP_VARIANT_AUTO, LUPP_VARIANT_THREAD, LUPP_VARIANT_LANES = 0, 1, 2
 LUPP_LAW_NORTON7, LUPP_LAW_NORTON_AF13 = 7, 13
-LUPP_E_UNSUPPORTED, LUPP_E_NOMEM, LUPP_E_HIP_BASE = -900, -901, -1000
+LUPP_E_UNSUPPORTED, LUPP_E_NOMEM, LUPP_E_TOO_LARGE, LUPP_E_HIP_BASE = -900, -901, -902, -1000
+LUPP_NOALLOC_MAX_BATCH = 4194304
 
 _P = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -75,6 +76,8 @@ _lupp_batched_solve_ragged = _sig("lupp_batched_solve_ragged", ctypes.c_int,
                                   [_P, _i64, _P, _P, _P, _P, _P, _P, _P, ctypes.c_uint, _P])
 _lupp_batched_solve_grouped = _sig("lupp_batched_solve_grouped", ctypes.c_int,
                                    [_P, ctypes.c_int, ctypes.POINTER(lupp_group), ctypes.c_uint, _P])
+_lupp_batched_solve_ragged_noalloc = _sig("lupp_batched_solve_ragged_noalloc", ctypes.c_int,
+                                          [_P, _i64, _P, _P, _P, _P, _P, _P, _P, ctypes.c_uint, _P])
 _lupp_force_variant = _sig("lupp_force_variant", ctypes.c_int,
                            [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int])
 _lupp_set_dispatch = _sig("lupp_set_dispatch", ctypes.c_int,
@@ -150,7 +153,8 @@ EXPORTED = ["lupp_create", "lupp_destroy", "lupp_batched_solve", "lupp_batched_s
             "lupp_sweep_destroy", "constitutive_update_batched", "lupp_set_newton_variant",
             "lupp_get_newton_variant", "lupp_set_pivoting", "lupp_get_pivoting",
             "lupp_ragged_lanes_supported", "lupp_set_ragged_lanes", "lupp_get_ragged_lanes",
-            "lupp_autotune_ragged", "lupp_batched_solve_grouped"]
+            "lupp_autotune_ragged", "lupp_batched_solve_ragged_noalloc",
+            "lupp_batched_solve_grouped"]
 
 
 class LuppError(RuntimeError):
@@ -246,6 +250,13 @@ def lupp_batched_solve_grouped(ctx: Context, groups, flags: int = 0, stream=None
     n = len(groups) if groups is not None else 0
     arr = (lupp_group * max(n, 1))(*groups) if n else None
     return _lupp_batched_solve_grouped(ctx.handle, n, arr, flags, _stream(stream))
+
+
+def lupp_batched_solve_ragged_noalloc(ctx: Context, batch: int, n, offA, offB, A, b, ipiv, info,
+                                      flags: int = 0, stream=None) -> int:
+    return _lupp_batched_solve_ragged_noalloc(ctx.handle, batch, _ptr(n), _ptr(offA), _ptr(offB),
+                                              _ptr(A), _ptr(b), _ptr(ipiv), _ptr(info), flags,
+                                              _stream(stream))
 
 
 def lupp_check_solve_args(n: int, batch: int, layout: int, A, lda: int, strideA: int, b,
