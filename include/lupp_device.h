@@ -105,16 +105,18 @@ __device__ __forceinline__ int pivot_tile_end(int k, int n, int tile)
  * k .. n-1 searched; ties go to the lowest row (position) either way.
  * Without kTile the solvers contain no tile code at all.
  *
- * kWaveSkip: the interchange of rows k and p costs select instructions for
- * every candidate row i (the row index p is data, the registers are not).
- * With kWaveSkip the swap with row i is done only if some lane of the wave
- * chose row i (a wave-uniform branch on a ballot), so a wave whose systems
- * pivot alike - the Jacobians of one law at neighbouring points, whose
- * pivots are nearly always row k or the flow-rule row - skips most of the
- * selects. The arithmetic, and so the result, is the same either way; for
- * unrelated random systems every row is some lane's pivot and the check
- * only adds one branch per candidate. */
-template <int N, bool kFactors, bool kFMA = false, bool kTile = false, bool kWaveSkip = false>
+ * Interchange: the pivot row p is data while register indices are not, so
+ * rows k and p are swapped by selects, one candidate row i at a time, and
+ * the swap with row i runs only if some lane of the wave chose it (a
+ * wave-uniform branch on a ballot). A wave whose systems pivot alike - the
+ * Jacobians of one law at neighbouring points, which nearly always pivot on
+ * row k or the flow-rule row - skips most of the selects; for unrelated
+ * random systems every row is some lane's pivot, and the branches still
+ * bound how far the compiler interleaves the swaps: measured on gfx950 this
+ * form needs far fewer registers than selecting the pivot row out of all
+ * candidates column by column (n = 8: 170 VGPRs against 256 plus scratch;
+ * n = 13: no scratch against 1204 bytes per lane). */
+template <int N, bool kFactors, bool kFMA = false, bool kTile = false>
 __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)[N],
                                                   int (&ipiv)[N], int tile = 0,
                                                   double thresh = 0.0)
@@ -158,53 +160,23 @@ __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)
         const bool zero = (pv == 0.0);
         info = (zero && info == 0) ? k + 1 : info;
 
-        /* interchange rows k and p */
-        if constexpr (kWaveSkip) {
-            /* one candidate row at a time, only where some lane picked it:
-             * exactly one i matches p in a lane, so the swaps compose to
-             * the single interchange (k, p) */
-            static_for<k + 1, N>(LUPP_SF(ic) {
-                constexpr int i = decltype(ic)::value;
-                const bool hit = (p == i);
-                if (__ballot(hit) != 0) {
-                    static_for<(kFactors ? 0 : k), N>(LUPP_SF(jc) {
-                        constexpr int j = decltype(jc)::value;
-                        const double rk = a[j][k], ri = a[j][i];
-                        a[j][k] = hit ? ri : rk;
-                        a[j][i] = hit ? rk : ri;
-                    });
-                    const double bk = b[k], bi = b[i];
-                    b[k] = hit ? bi : bk;
-                    b[i] = hit ? bk : bi;
-                }
-            });
-        } else {
-            static_for<(kFactors ? 0 : k), N>(LUPP_SF(jc) {
-                constexpr int j = decltype(jc)::value;
-                const double rk = a[j][k];
-                double rp = rk;
-                static_for<k + 1, N>(LUPP_SF(ic) {
-                    constexpr int i = decltype(ic)::value;
-                    rp = (p == i) ? a[j][i] : rp;
+        /* interchange rows k and p: exactly one candidate i matches p in a
+         * lane, so the conditional swaps compose to the single interchange */
+        static_for<k + 1, N>(LUPP_SF(ic) {
+            constexpr int i = decltype(ic)::value;
+            const bool hit = (p == i);
+            if (__ballot(hit) != 0) {
+                static_for<(kFactors ? 0 : k), N>(LUPP_SF(jc) {
+                    constexpr int j = decltype(jc)::value;
+                    const double rk = a[j][k], ri = a[j][i];
+                    a[j][k] = hit ? ri : rk;
+                    a[j][i] = hit ? rk : ri;
                 });
-                static_for<k + 1, N>(LUPP_SF(ic) {
-                    constexpr int i = decltype(ic)::value;
-                    a[j][i] = (p == i) ? rk : a[j][i];
-                });
-                a[j][k] = rp;
-            });
-            const double rk = b[k];
-            double rp = rk;
-            static_for<k + 1, N>(LUPP_SF(ic) {
-                constexpr int i = decltype(ic)::value;
-                rp = (p == i) ? b[i] : rp;
-            });
-            static_for<k + 1, N>(LUPP_SF(ic) {
-                constexpr int i = decltype(ic)::value;
-                b[i] = (p == i) ? rk : b[i];
-            });
-            b[k] = rp;
-        }
+                const double bk = b[k], bi = b[i];
+                b[k] = hit ? bi : bk;
+                b[i] = hit ? bk : bi;
+            }
+        });
 
         if (!zero) {
             /* multipliers, Schur-complement update, forward substitution */
@@ -294,14 +266,11 @@ __device__ __forceinline__ void thread_solve_unit(const double (&lu)[N][N], cons
 }
 
 /* Solve-only convenience entry: the device-callable solve of one system held
- * by the calling thread (a is destroyed). Returns info. Meant for calls from
- * per-point code such as a Newton loop, where the lanes of a wave solve
- * systems of one structure: interchanges no lane of the wave needs are
- * skipped (kWaveSkip). */
+ * by the calling thread (a is destroyed). Returns info. */
 template <int N>
 __device__ __forceinline__ int lupp_solve_n(double (&a)[N][N], double (&b)[N], int (&ipiv)[N])
 {
-    return thread_getrf_solve<N, false, false, false, true>(a, b, ipiv);
+    return thread_getrf_solve<N, false>(a, b, ipiv);
 }
 
 /* ------------------------------------------------------------------------ */

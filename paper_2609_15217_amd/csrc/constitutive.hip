@@ -72,7 +72,7 @@ __device__ __forceinline__ void newton_block(const lupp_points &pts, const LawK 
         int piv[NU];
 #pragma unroll
         for (int i = 0; i < NU; ++i) dx[i] = -F[i];
-        if (thread_getrf_solve<NU, false, false, false, true>(J, dx, piv) != 0) { status = 2; break; }
+        if (thread_getrf_solve<NU, false>(J, dx, piv) != 0) { status = 2; break; }
 #pragma unroll
         for (int i = 0; i < NU; ++i) Y(i) = Y(i) + dx[i];
     }

@@ -20,11 +20,12 @@
 
 namespace lupp {
 
-/* Occupancy target per size: the register-resident matrix takes 2*N*N VGPRs,
- * so small systems leave room for several waves per SIMD to hide latency,
- * while n >= 9 needs most of the 512-entry register file of one wave. */
+/* Occupancy target per size: the register-resident matrix takes 2*N*N VGPRs.
+ * Each value is the highest occupancy the compiler reaches for that size
+ * without scratch memory (gfx950: n <= 6 at 4 or more waves per SIMD, n = 7
+ * and 8 at 3, n = 9 and 10 at 2 - 208 and 250 VGPRs -, n >= 11 at 1). */
 template <int N>
-constexpr int thread_waves_per_eu() { return N <= 4 ? 4 : (N <= 8 ? 2 : 1); }
+constexpr int thread_waves_per_eu() { return N <= 6 ? 4 : (N <= 8 ? 3 : (N <= 10 ? 2 : 1)); }
 
 template <int N, bool F, bool Tl>
 __global__ void __launch_bounds__(256)

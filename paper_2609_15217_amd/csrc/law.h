@@ -261,7 +261,7 @@ __device__ __forceinline__ void newton_tangent7(const LawK &P, const double (&de
     law_assemble<7>(P, de, st, y, Fc, J, sc);
 #pragma unroll
     for (int i = 0; i < 7; ++i) z[i] = 0.0;
-    const bool sing = thread_getrf_solve<7, true, false, false, true>(J, z, piv) != 0;
+    const bool sing = thread_getrf_solve<7, true>(J, z, piv) != 0;
     thread_ipiv_to_perm<7>(piv, perm);
 #pragma unroll 1
     for (int c = 0; c < 6; ++c) {
@@ -292,7 +292,7 @@ static __device__ __forceinline__ void newton_tangent13(const LawK &P, const dou
         law_assemble<13>(P, de, st, y, Fc, J, sc);
 #pragma unroll
         for (int i = 0; i < 13; ++i) x[i] = (i == c) ? 1.0 : 0.0;
-        const bool sing = thread_getrf_solve<13, false, false, false, true>(J, x, piv) != 0;
+        const bool sing = thread_getrf_solve<13, false>(J, x, piv) != 0;
         tangent_store_col<13>(P, pts, p0, nb, vo, c, x, sing);
     }
 }
