@@ -48,9 +48,10 @@ extern "C" {
 #define LUPP_SOA 1
 
 /* Flags. LUPP_KEEP_A: do not write the factors back (A is left unchanged).
- * LUPP_RAGGED_PER_SIZE (lupp_batched_solve_ragged only): instead of the one
- * persistent launch, read the size histogram back to the host and launch one
- * kernel per size (the plain baseline; it synchronises the stream).
+ * LUPP_RAGGED_PER_SIZE (lupp_batched_solve_ragged only): instead of the
+ * launches per size class, read the size histogram back to the host and
+ * launch one kernel per size (the plain baseline; it synchronises the
+ * stream).
  * LUPP_FMA (lupp_batched_solve only): fused multiply-add arithmetic, see
  * lupp_batched_solve. */
 #define LUPP_KEEP_A 1u
@@ -102,7 +103,14 @@ int lupp_get_device(const lupp_ctx *ctx, int *device);
  *             as in strict mode); results are then bitwise those of the
  *             oracle's FMA mode rather than of the strict default. Not
  *             combined with tile-local pivoting (LUPP_E_UNSUPPORTED).
- * Inputs containing NaN or Inf produce unspecified factors and info. */
+ * Inputs containing NaN or Inf produce unspecified factors and info.
+ * Address range: the kernels address memory through 32-bit offsets from
+ * per-workgroup bases. AoS takes any batch while 256 * strideA * 8 and
+ * 256 * strideB * 8 stay below 2^31 bytes. SoA with the thread variant takes
+ * any ldbatch; the lanes variant needs 3 * ldbatch * 8 + 128 < 2^31 bytes
+ * (ldbatch below 89,478,485; 2-lane segments: twice that) - beyond it sizes
+ * up to 13 switch to the thread variant and larger sizes return
+ * LUPP_E_UNSUPPORTED. */
 int lupp_batched_solve(lupp_ctx *ctx, int n, int64_t batch, int layout, double *A, int64_t lda,
                        int64_t strideA, double *b, int64_t strideB, int32_t *ipiv,
                        int32_t *info, unsigned flags, void *stream);
@@ -120,10 +128,10 @@ int lupp_check_solve_args(int n, int64_t batch, int layout, const double *A, int
  * Systems must not overlap. n, offA, offB are device arrays of `batch`
  * (<= 2^31 - 1) entries. The library groups systems by size on the device
  * (histogram, plan, scatter; workspace owned by the context, grown with
- * hipMalloc when a larger batch arrives) and serves the sizes from two
- * persistent kernel launches queued back to back on `stream` (sizes 17..32,
- * then 1..16: each kernel's register budget fits its sizes), largest sizes
- * first; no host synchronisation. Each size uses the lane count of the
+ * hipMalloc when a larger batch arrives) and serves the sizes from one
+ * kernel launch per size class queued back to back on `stream` (sizes
+ * 24..32, 17..23, then 1..16: each kernel's register budget fits its sizes),
+ * largest sizes first; no host synchronisation. Each size uses the lane count of the
  * context's ragged table (lupp_set_ragged_lanes). A system whose n is
  * outside 1..32 gets info = -1 and is not touched. flags: LUPP_KEEP_A,
  * LUPP_RAGGED_PER_SIZE.
@@ -201,7 +209,7 @@ int lupp_ragged_lanes_supported(int n, int lanes);
 int lupp_set_ragged_lanes(lupp_ctx *ctx, int n, int lanes);
 int lupp_get_ragged_lanes(const lupp_ctx *ctx, int n);
 
-/* Autotune the ragged lane count of size n: time the persistent ragged path
+/* Autotune the ragged lane count of size n: time the ragged path
  * (the same call lupp_batched_solve_ragged makes) on `batch` systems of size
  * n for every supported lane count, keep the fastest in the context's ragged
  * table and report it (lanes, median ms). A is `batch` packed column-major
@@ -345,8 +353,7 @@ int lupp_get_newton_variant(const lupp_ctx *ctx, int kind, int *lanes);
  *   flags      : 0, or LUPP_BATCHED_GRAPH to capture one iteration in a HIP
  *                graph and replay it (one launch per iteration).
  *   iterations : NULL, or receives the number of host-driven iterations.
- * Returns as constitutive_update, -6 for unknown flags, LUPP_E_UNSUPPORTED if
- * (kind^2 + 1) * count * 8 bytes reach 2^31. */
+ * Returns as constitutive_update, or -6 for unknown flags. */
 #define LUPP_BATCHED_GRAPH 1u
 int constitutive_update_batched(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law,
                                 double tol, int maxit, unsigned flags, void *stream,

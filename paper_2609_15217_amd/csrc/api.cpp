@@ -51,10 +51,17 @@ static bool fits_offsets(int n, int64_t batch, int layout, int variant, int lane
                          int64_t sA, int64_t sB)
 {
     const int64_t lim = (int64_t)1 << 31;
-    (void)variant;
+    (void)batch;
+    (void)n;
     if (layout == LUPP_SOA) {
-        (void)batch;
-        return ((int64_t)(n - 1) * sA + 256) * 8 < lim && ((int64_t)(n - 1) * sB + 256) * 8 < lim;
+        /* the thread kernel bases one descriptor at every element: its
+         * extents cover one workgroup's systems, any ldbatch fits */
+        if (variant == LUPP_VARIANT_THREAD) return true;
+        /* the staged kernel's descriptors span the rows one wave moves:
+         * 64/S rows of S systems, S = max(64/lanes, 16) */
+        const int64_t S = 64 / lanes > 16 ? 64 / lanes : 16;
+        const int64_t rows = 64 / S;
+        return ((rows - 1) * sA + S) * 8 < lim && ((rows - 1) * sB + S) * 8 < lim;
     }
     const int64_t per = variant == LUPP_VARIANT_THREAD ? 256 : 64 / (lanes > 0 ? lanes : 1);
     return per * sA * 8 < lim && per * sB * 8 < lim && per * n * 4 < lim;
@@ -225,8 +232,14 @@ int lupp_batched_solve(lupp_ctx *ctx, int n, int64_t batch, int layout, double *
         c = Choice{ctx->forced_variant, ctx->forced_lanes, ctx->forced_wpb};
     LaunchFn fn = pick(n, c);
     if (fn == nullptr) return LUPP_E_UNSUPPORTED;
-    if (!fits_offsets(n, batch, layout, c.variant, c.lanes, strideA, strideB))
-        return LUPP_E_UNSUPPORTED;
+    if (!fits_offsets(n, batch, layout, c.variant, c.lanes, strideA, strideB)) {
+        /* an interleaved batch too far apart for the staged lanes kernel:
+         * the thread kernel takes any ldbatch (sizes it is compiled for) */
+        if (layout != LUPP_SOA || n > kThreadMaxN) return LUPP_E_UNSUPPORTED;
+        c = Choice{LUPP_VARIANT_THREAD, 1, 0};
+        fn = pick(n, c);
+        if (fn == nullptr) return LUPP_E_UNSUPPORTED;
+    }
     int cur = 0;
     hipGetDevice(&cur);
     if (cur != ctx->device) hipSetDevice(ctx->device);
@@ -535,9 +548,6 @@ int constitutive_update_batched(lupp_ctx *ctx, const lupp_points *pts, const lup
     if (pts->deps == nullptr || pts->state == nullptr || pts->sig == nullptr ||
         pts->iters == nullptr || pts->status == nullptr)
         return -2;
-    /* the batched SoA solve addresses the largest Jacobian row with 32 bits */
-    if (((int64_t)law->kind * law->kind + 1) * pts->count * 8 >= ((int64_t)1 << 31))
-        return LUPP_E_UNSUPPORTED;
     int cur = 0;
     hipGetDevice(&cur);
     if (cur != ctx->device) hipSetDevice(ctx->device);

@@ -77,7 +77,7 @@ int ragged_launch_impl(RaggedWs *ws, const uint8_t *lanes, int64_t batch, const 
                        const int64_t *offA, const int64_t *offB, double *A, double *b,
                        int32_t *ipiv, int32_t *info, bool factors, bool per_size,
                        hipStream_t stream);
-/* Time the persistent ragged path on a batch of `batch` systems of size n
+/* Time the ragged path (class launches) on a batch of `batch` systems of size n
  * (AoS, packed) for every lane count compiled for n; lanes[n] is left at the
  * fastest (median of reps timed runs after one warm-up). */
 int ragged_autotune_impl(RaggedWs *ws, uint8_t *lanes, int n, int64_t batch, const double *A,
@@ -96,16 +96,16 @@ int noalloc_ragged_enqueue(int device, const uint8_t *lanes, int64_t batch, cons
  * the autotuner's table); false if the table has no entry for n. */
 bool tuned_ragged(int n, int *lanes);
 
-/* Sizes above this one are served by the large-size ragged kernel. */
+/* Sizes above this one run in the ragged kernels of 16-lane segments. */
 constexpr int kRaggedSmallMax = 16;
 
 /* Lane counts compiled into the ragged kernels for size n. Sizes up to 16
- * share one kernel held to 128 VGPRs (4 waves per SIMD): the thread path up
- * to n = 5 and segments of 2, 4, 8 or 16 lanes where the rows fit; sizes
- * 17..32 run in a kernel with up to 256 VGPRs (2 waves per SIMD) with 16
- * lanes, two rows each (one row on each of 32 lanes measured slower at every
- * one of these sizes, standalone and in the ragged kernel, so it is not
- * compiled in: it would double the kernel's code). */
+ * share one kernel held to 3 waves per SIMD: the thread path up to n = 5 and
+ * segments of 2, 4, 8 or 16 lanes where the rows fit; sizes 17..32 run in two
+ * kernels (17..23 at 3 waves per SIMD, 24..32 at 2) with 16 lanes, two rows
+ * each (one row on each of 32 lanes measured slower at every one of these
+ * sizes, standalone and in the ragged kernel, so it is not compiled in: it
+ * would double the kernels' code). */
 __host__ __device__ constexpr bool ragged_lanes_ok(int n, int T)
 {
     if (n < 1 || n > 32) return false;
@@ -191,6 +191,15 @@ __device__ __forceinline__ T *opaque_ptr(T *p)
     uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     asm volatile("" : "+s"(lo), "+s"(hi));
     return (T *)(((uint64_t)hi << 32) | lo);
+}
+
+/* The same for a uniform 64-bit integer (strides and offsets). */
+__device__ __forceinline__ int64_t opaque_i64(int64_t v)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 inline int hip_err(hipError_t e) { return e == hipSuccess ? 0 : LUPP_E_HIP_BASE - (int)e; }

@@ -93,13 +93,19 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
     /* lane side: system yl, rows t + s*T */
     const int yl = wave * Sh::SPW + g;
 
-    double *baseA = a.A + sys0;
-    double *baseB = a.b + sys0;
+    /* The cooperative rows of a wave are ci0 = cw .. cw + 64/S - 1, so each
+     * descriptor is based at the wave's first row (a uniform address) and
+     * its extent spans 64/S rows: the per-lane offsets stay below 2^31
+     * bytes for any ldbatch under 2^31 / (8 * (64/S - 1) + 8). */
+    const int cw = (wave * 64) >> Sh::LOG_S;
+    double *baseA = a.A + sys0 + (int64_t)cw * a.sA;
+    double *baseB = a.b + sys0 + (int64_t)cw * a.sB;
     const int64_t colA = a.lda * a.sA;
-    const uint32_t bytesA = (uint32_t)(((int64_t)(N - 1) * a.sA + nvalid) * 8);
-    const uint32_t bytesB = (uint32_t)(((int64_t)(N - 1) * a.sB + nvalid) * 8);
-    const uint32_t vA = yw < nvalid ? (uint32_t)(((int64_t)ci0 * a.sA + yw) * 8) : kOutOfRange;
-    const uint32_t vB = yw < nvalid ? (uint32_t)(((int64_t)ci0 * a.sB + yw) * 8) : kOutOfRange;
+    constexpr int RW = 64 / S; /* cooperative rows per wave */
+    const uint32_t bytesA = (uint32_t)(((int64_t)(RW - 1) * a.sA + nvalid) * 8);
+    const uint32_t bytesB = (uint32_t)(((int64_t)(RW - 1) * a.sB + nvalid) * 8);
+    const uint32_t vA = yw < nvalid ? (uint32_t)(((int64_t)(ci0 - cw) * a.sA + yw) * 8) : kOutOfRange;
+    const uint32_t vB = yw < nvalid ? (uint32_t)(((int64_t)(ci0 - cw) * a.sB + yw) * 8) : kOutOfRange;
     /* per-lane offset of the cooperative row ci0 + ib (out of range for rows past n) */
     auto rowv = [&](uint32_t v, int ib) -> uint32_t {
         return (ib + T <= N || ci0 < N - ib) ? v : kOutOfRange;
@@ -125,14 +131,14 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
     static_for<0, N * QB>(LUPP_SF(qc) {
         constexpr int q = decltype(qc)::value;
         constexpr int j = q / QB, ib = (q % QB) * T;
-        const auto rc = make_rsrc(baseA + (int64_t)j * colA, bytesA);
-        v[q] = buf_load_f64(rc, rowv(vA, ib), (uint32_t)((int64_t)ib * a.sA * 8));
+        const auto rc = make_rsrc(baseA + (int64_t)j * colA + (int64_t)ib * a.sA, bytesA);
+        v[q] = buf_load_f64(rc, rowv(vA, ib), 0);
     });
     {
-        const auto rb = make_rsrc(baseB, bytesB);
         static_for<0, QB>(LUPP_SF(qc) {
             constexpr int ib = decltype(qc)::value * T;
-            vb[decltype(qc)::value] = buf_load_f64(rb, rowv(vB, ib), (uint32_t)((int64_t)ib * a.sB * 8));
+            vb[decltype(qc)::value] =
+                buf_load_f64(make_rsrc(baseB + (int64_t)ib * a.sB, bytesB), rowv(vB, ib), 0);
         });
     }
     static_for<0, NCH>(LUPP_SF(chc) {
@@ -181,6 +187,7 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
     /* ---------------------------------------------------------- store */
     baseA = opaque_ptr(baseA);
     baseB = opaque_ptr(baseB);
+    const int64_t sAs = opaque_i64(a.sA), sBs = opaque_i64(a.sB);
     if (factors) {
         static_for<0, NCH>(LUPP_SF(chc) {
             constexpr int j0 = decltype(chc)::value * CJ;
@@ -199,8 +206,8 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
             static_for<0, cj * QB>(LUPP_SF(qc) {
                 constexpr int q = decltype(qc)::value;
                 constexpr int c = q / QB, ib = (q % QB) * T;
-                const auto rc = make_rsrc(baseA + (int64_t)(j0 + c) * colA, bytesA);
-                buf_store_f64(rc, rowv(vA, ib), (uint32_t)((int64_t)ib * a.sA * 8), tile[cidx(c, ib)]);
+                const auto rc = make_rsrc(baseA + (int64_t)(j0 + c) * colA + (int64_t)ib * sAs, bytesA);
+                buf_store_f64(rc, rowv(vA, ib), 0, tile[cidx(c, ib)]);
             });
             __syncthreads();
         });
@@ -218,14 +225,15 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
     __syncthreads();
     {
         const bool ok = infl[yw] == 0;
-        const auto rb = make_rsrc(baseB, bytesB);
-        const auto rp = make_rsrc(a.ipiv + sys0, (uint32_t)(((int64_t)(N - 1) * a.sA + nvalid) * 4));
-        const uint32_t vP = yw < nvalid ? (uint32_t)(((int64_t)ci0 * a.sA + yw) * 4) : kOutOfRange;
+        int32_t *baseP = a.ipiv + sys0 + (int64_t)cw * sAs;
+        const uint32_t bytesP = (uint32_t)(((int64_t)(RW - 1) * sAs + nvalid) * 4);
+        const uint32_t vP = yw < nvalid ? (uint32_t)(((int64_t)(ci0 - cw) * sAs + yw) * 4) : kOutOfRange;
         static_for<0, QB>(LUPP_SF(qc) {
             constexpr int ib = decltype(qc)::value * T;
-            buf_store_f64(rb, ok ? rowv(vB, ib) : kOutOfRange, (uint32_t)((int64_t)ib * a.sB * 8),
-                          xb[cidx(0, ib)]);
-            buf_store_i32(rp, rowv(vP, ib), (uint32_t)((int64_t)ib * a.sA * 4), ipl[cidx(0, ib)]);
+            buf_store_f64(make_rsrc(baseB + (int64_t)ib * sBs, bytesB), ok ? rowv(vB, ib) : kOutOfRange,
+                          0, xb[cidx(0, ib)]);
+            buf_store_i32(make_rsrc(baseP + (int64_t)ib * sAs, bytesP), rowv(vP, ib), 0,
+                          ipl[cidx(0, ib)]);
         });
         const auto ri = make_rsrc(a.info + sys0, (uint32_t)nvalid * 4u);
         if (tid < S) buf_store_i32(ri, (uint32_t)tid * 4u, 0, infl[tid]);

@@ -40,20 +40,21 @@ __global__ void __launch_bounds__(256)
     const bool active = tid < nvalid;
 
     /* Element (i, j) of this lane's system sits at
-     *   colbase_j + i*R + tid*V   (elements), colbase_j = base + j*C,
+     *   base + j*C + i*R + tid*V   (elements),
      * SoA: base = A + s0, C = lda*ldbatch, R = ldbatch, V = 1;
      * AoS: base = A + s0*strideA, C = lda, R = 1, V = strideA.
-     * One descriptor per column; the row offset i*R goes in the uniform
-     * offset field and the lane offset in the VGPR. Descriptor extents cover
-     * exactly the valid lanes' elements, and lanes past the batch get an
-     * out-of-range lane offset. */
+     * Every element gets its own descriptor based at base + j*C + i*R (a
+     * uniform 64-bit address built with scalar adds), so the descriptor
+     * extent covers only the workgroup's lanes - nvalid*V elements - whatever
+     * the strides: an interleaved batch may span any number of bytes. Lanes
+     * past the batch get an out-of-range lane offset. */
     double *bA = a.A + (soa ? s0 : s0 * a.sA);
     double *bB = a.b + (soa ? s0 : s0 * a.sB);
     const int64_t C = soa ? a.lda * a.sA : a.lda;
-    const uint32_t R8 = (uint32_t)((soa ? a.sA : 1) * 8);
-    const uint32_t RB8 = (uint32_t)((soa ? a.sB : 1) * 8);
-    const uint32_t nbA = soa ? (uint32_t)(((int64_t)(N - 1) * a.sA + nvalid) * 8) : nvalid * (uint32_t)a.sA * 8u;
-    const uint32_t nbB = soa ? (uint32_t)(((int64_t)(N - 1) * a.sB + nvalid) * 8) : nvalid * (uint32_t)a.sB * 8u;
+    const int64_t R = soa ? a.sA : 1;
+    const int64_t RB = soa ? a.sB : 1;
+    const uint32_t nbA = nvalid * (uint32_t)(soa ? 8 : a.sA * 8);
+    const uint32_t nbB = nvalid * (uint32_t)(soa ? 8 : a.sB * 8);
     const uint32_t voA = !active ? kOutOfRange : (soa ? tid * 8u : tid * (uint32_t)a.sA * 8u);
     const uint32_t voB = !active ? kOutOfRange : (soa ? tid * 8u : tid * (uint32_t)a.sB * 8u);
 
@@ -62,52 +63,52 @@ __global__ void __launch_bounds__(256)
     int piv[N];
     static_for<0, N>([&](auto jc) __attribute__((always_inline)) {
         constexpr int j = decltype(jc)::value;
-        const auto r = make_rsrc(bA + j * C, nbA);
         static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
             constexpr int i = decltype(ic)::value;
-            m[j][i] = buf_load_f64(r, voA, i * R8);
+            m[j][i] = buf_load_f64(make_rsrc(bA + j * C + i * R, nbA), voA, 0);
         });
+        asm volatile("" ::: "memory");
     });
     {
-        const auto r = make_rsrc(bB, nbB);
         static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
             constexpr int i = decltype(ic)::value;
-            x[i] = buf_load_f64(r, voB, i * RB8);
+            x[i] = buf_load_f64(make_rsrc(bB + i * RB, nbB), voB, 0);
         });
     }
 
     const int inf = thread_getrf_solve<N, true, F, Tl>(m, x, piv, a.tile, a.thresh);
 
+    /* fresh copies of the bases and strides: the store addresses are then
+     * rebuilt here instead of being kept live (in SGPRs) across the solve */
     bA = opaque_ptr(bA);
     bB = opaque_ptr(bB);
+    const int64_t Cs = opaque_i64(C), Rs = opaque_i64(R), RBs = opaque_i64(RB);
     if (factors) {
         static_for<0, N>([&](auto jc) __attribute__((always_inline)) {
             constexpr int j = decltype(jc)::value;
-            const auto r = make_rsrc(bA + j * C, nbA);
             static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
                 constexpr int i = decltype(ic)::value;
-                buf_store_f64(r, voA, i * R8, m[j][i]);
+                buf_store_f64(make_rsrc(bA + j * Cs + i * Rs, nbA), voA, 0, m[j][i]);
             });
+            asm volatile("" ::: "memory");
         });
     }
     {
-        const auto r = make_rsrc(bB, nbB);
         const uint32_t vx = inf == 0 ? voB : kOutOfRange;
         static_for<0, N>([&](auto ic) __attribute__((always_inline)) {
             constexpr int i = decltype(ic)::value;
-            buf_store_f64(r, vx, i * RB8, x[i]);
+            buf_store_f64(make_rsrc(bB + i * RBs, nbB), vx, 0, x[i]);
         });
     }
     /* AoS ipiv[s*N + k]; SoA ipiv[k*ldbatch + s] */
     {
         int32_t *bP = opaque_ptr(a.ipiv + (soa ? s0 : s0 * N));
-        const uint32_t nbP = soa ? (uint32_t)(((int64_t)(N - 1) * a.sA + nvalid) * 4) : nvalid * N * 4u;
+        const uint32_t nbP = nvalid * (soa ? 4u : N * 4u);
         const uint32_t voP = !active ? kOutOfRange : (soa ? tid * 4u : tid * N * 4u);
-        const uint32_t RP4 = (uint32_t)((soa ? a.sA : 1) * 4);
-        const auto r = make_rsrc(bP, nbP);
+        const int64_t RP = soa ? a.sA : 1;
         static_for<0, N>([&](auto kc) __attribute__((always_inline)) {
             constexpr int k = decltype(kc)::value;
-            buf_store_i32(r, voP, k * RP4, piv[k]);
+            buf_store_i32(make_rsrc(bP + k * RP, nbP), voP, 0, piv[k]);
         });
     }
     buf_store_i32(make_rsrc(a.info + s0, nvalid * 4u), tid * 4u, 0, inf);

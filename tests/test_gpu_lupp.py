@@ -239,3 +239,56 @@ def test_full_size_sweep_sampled(L, ctx, n):
     # forward error against the known solution (kappa_2 <= 1e4)
     fe = np.abs(tb.cpu().numpy().T - xt).max(axis=1) / np.abs(xt).max(axis=1)
     assert fe.max() < 1e-9
+
+
+def solve_far_apart(L, ctx, A, b, ld, variant, lanes):
+    """SoA solve of A, b (AoS numpy) placed in an interleaved array whose
+    ldbatch `ld` puts the rows of the batch far apart (beyond 2 GiB); only
+    the first batch columns of each row are written and read back."""
+    batch, n = A.shape[0], A.shape[1]
+    dev = torch.device("cuda:0")
+    tA = torch.empty((n * n, ld), dtype=torch.float64, device=dev)
+    tb = torch.empty((n, ld), dtype=torch.float64, device=dev)
+    ipiv = torch.empty((n, ld), dtype=torch.int32, device=dev)
+    info = torch.full((batch,), -7, dtype=torch.int32, device=dev)
+    tA[:, :batch] = torch.from_numpy(aos_to_soa(A).reshape(n * n, batch)).to(dev)
+    tb[:, :batch] = torch.from_numpy(aos_to_soa(b)).to(dev)
+    assert L.lupp_force_variant(ctx, variant, lanes, 0) == 0
+    try:
+        rc = L.lupp_batched_solve(ctx, n, batch, L.LUPP_SOA, tA, n, ld, tb, ld, ipiv, info)
+    finally:
+        L.lupp_force_variant(ctx, 0, 0, 0)
+    assert rc == 0, L.lupp_error_string(rc)
+    torch.cuda.synchronize()
+    LU = tA[:, :batch].cpu().numpy().reshape(n, n, batch).transpose(2, 0, 1)
+    x = tb[:, :batch].cpu().numpy().T
+    pv = ipiv[:, :batch].cpu().numpy().T
+    io = info.cpu().numpy()
+    del tA, tb, ipiv, info
+    torch.cuda.empty_cache()
+    return LU, x, pv, io
+
+
+@pytest.mark.parametrize("n,variant,lanes,ld", [
+    (6, 1, 0, 60_000_000),   # thread kernel: (n-1) * ldbatch * 8 > 2 GiB
+    (8, 2, 8, 40_000_000),   # staged lanes kernel, 8-lane segments
+    (16, 2, 16, 18_000_000),  # staged lanes kernel, 16-lane segments
+    (3, 2, 4, 90_000_000),   # beyond the lanes kernel's range: thread kernel
+])
+def test_interleaved_batches_beyond_2gib(L, ctx, n, variant, lanes, ld):
+    """Interleaved batches whose rows lie more than 2^31 bytes apart (up to
+    37 GB of address range) solve bitwise as the oracle does."""
+    A, b, _ = systems(n, 1000, seed=7600 + n)
+    ref = oracle.gesv_batch(A, b, threads=8)
+    LU, x, pv, io = solve_far_apart(L, ctx, A, b, ld, variant, lanes)
+    assert_same(ref, LU, x, pv, io)
+
+
+def test_interleaved_batch_out_of_range_is_refused(L, ctx):
+    """n = 20 has no thread kernel: an ldbatch beyond the lanes kernel's
+    32-bit range is refused on the host, before anything is launched."""
+    dev = torch.device("cuda:0")
+    t = torch.zeros(64, dtype=torch.float64, device=dev)
+    ti = torch.zeros(64, dtype=torch.int32, device=dev)
+    rc = L.lupp_batched_solve(ctx, 20, 10, L.LUPP_SOA, t, 20, 90_000_000, t, 90_000_000, ti, ti)
+    assert rc == L.LUPP_E_UNSUPPORTED
