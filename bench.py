@@ -4,12 +4,12 @@ systems, and the fused Newton constitutive update, on one MI355X.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 
 One step = one pass of the standalone-solve sweep: 2^20 independent systems
-for each n in {4, 8, 12, 16, 24, 32} (A ~ N(0,1) resampled while
+for each n in {8, 12, 16, 24, 32} (A ~ N(0,1) resampled while
 cond2(A) > 1e4, b = A x_true, x_true ~ U(-1,1)), solved in the interleaved
-SoA layout and in the AoS layout (24 launches of lupp_batched_solve). The
+SoA layout and in the AoS layout (10 launches of lupp_batched_solve). The
 solve is in place, so every step starts from inputs restored from a pristine
 device copy outside the timed region. `value` is systems solved per second
-over the timed steps.
+over the timed steps. n = 4 is timed beside the step (the 4..32 figure).
 
 Also reported: the fused Newton update (2^20 points, Norton 7x7 and
 Norton+Armstrong-Frederick 13x13), per-call latency p50/p99 of a 4096-system
@@ -52,6 +52,16 @@ def flops_per_system(n: int) -> int:
     """Factorisation sum_{m=1}^{n-1} (m + 2 m^2) plus the two triangular
     solves 2 n^2 - n."""
     return sum(m + 2 * m * m for m in range(1, n)) + 2 * n * n - n
+
+
+# Operations (add, sub, mul, div, sqrt, pow: one each) of one evaluation of
+# the law's residual and exact Jacobian (Section 2.1, eqs. 1-3) as the oracle's
+# law routine executes them, counted by compiling that routine against a
+# counting number type (oracle/law_flops.py; a test keeps these values equal
+# to its output). The oracle forms the Jacobian with full 6 x 6 products by
+# the deviatoric projector, so the figure bounds from above what the law
+# needs. A point evaluates the law at every iterate: solves + 1 times.
+LAW_FLOPS = {7: 869, 13: 1331}
 
 
 def log(msg: str):
@@ -525,7 +535,7 @@ def main():
         n64 = mx["n"].astype(np.int64)
         alg_bytes = int((16 * n64 * n64 + 20 * n64 + 4).sum()) + nb * (4 + 16)
         alg_flops = int(sum(flops_per_system(n) * int((mx["n"] == n).sum()) for n in range(2, 33)))
-        for mode, flags in (("persistent", 0), ("per_size", L.LUPP_RAGGED_PER_SIZE)):
+        for mode, flags in (("class_launches", 0), ("per_size", L.LUPP_RAGGED_PER_SIZE)):
             times = []
             for r in range(args.warmup + args.steps):
                 wA.copy_(pA)
@@ -550,8 +560,8 @@ def main():
                               "cond2 > 1e4, AoS packed with int64 offsets, seed 3")
         ragged["algorithmic_bytes"] = alg_bytes
         ragged["lanes_per_size"] = {n: L.lupp_get_ragged_lanes(ctx, n) for n in range(1, 33)}
-        ragged["speedup_persistent_vs_per_size"] = round(
-            ragged["per_size"]["ms"] / ragged["persistent"]["ms"], 3)
+        ragged["speedup_classes_vs_per_size"] = round(
+            ragged["per_size"]["ms"] / ragged["class_launches"]["ms"], 3)
         del tn, toA, toB, pA, pb, wA, wb, rip, rin, mx
         torch.cuda.empty_cache()
 
@@ -689,6 +699,16 @@ def main():
                                        "solve_fp64_frac": round(
                                            its * flops_per_system(kind) / (ms * 1e-3) / 1e12
                                            / FP64_PEAK_TFLOPS, 4),
+                                       # the same plus the law at every iterate, counted
+                                       # on the oracle's formulation (LAW_FLOPS)
+                                       "fp64_TFLOPs_with_law": round(
+                                           (its * flops_per_system(kind)
+                                            + (its + count) * LAW_FLOPS[kind])
+                                           / (ms * 1e-3) / 1e12, 3),
+                                       "fp64_frac_with_law": round(
+                                           (its * flops_per_system(kind)
+                                            + (its + count) * LAW_FLOPS[kind])
+                                           / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
                                        "converged": conv,
                                        "default_lanes_per_point": default_lanes,
                                        "mapping": mapping,

@@ -8,7 +8,7 @@ size in the ragged (mixed-size) path, and write dispatch_gfx950.json
 Each standalone entry is chosen by lupp_autotune (a C-ABI call that times
 every compiled variant and workgroup size on a device copy of the batch and
 keeps the median-fastest); each ragged entry by lupp_autotune_ragged (the
-persistent ragged path timed on a batch of one size large enough that the
+ragged path, one launch per size class, timed on a batch of one size large enough that the
 solve, not the grouping kernels, dominates: 2^20 systems up to n = 16, 2^19
 above). With --what, the part not measured is kept from the existing file.
 """

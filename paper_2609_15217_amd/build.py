@@ -232,7 +232,7 @@ def _weight(src: str) -> int:
     if b.startswith("thread_"):
         n = int(b[7:-4])
         return 4 * n ** 3
-    if b in ("ragged_large.hip", "ragged_small.hip"):
+    if b.startswith(("ragged_c", "grouped_c")):
         return 400_000
     if b.startswith("ragged"):
         return 200_000

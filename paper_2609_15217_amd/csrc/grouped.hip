@@ -28,21 +28,21 @@ int grouped_enqueue_each(const lupp_group *groups, const uint8_t *factors_of, bo
         if (groups[i].batch > 0) order.push_back(i);
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return groups[x].n > groups[y].n; });
-    for (int cls = 0; cls < 2; ++cls) {
-        const bool large = cls == 0;
+    for (int cls = 0; cls < kRaggedClasses; ++cls) {
         GroupedArgs a{};
         int64_t items = 0;
         auto flush = [&]() -> hipError_t {
             if (a.ngroups == 0) return hipSuccess;
-            const hipError_t e = large ? grouped_large_launch(a, (unsigned)items, st)
-                                       : grouped_small_launch(a, (unsigned)items, st);
+            const hipError_t e = cls == 0   ? grouped_c0_launch(a, (unsigned)items, st)
+                                 : cls == 1 ? grouped_c1_launch(a, (unsigned)items, st)
+                                            : grouped_c2_launch(a, (unsigned)items, st);
             a = GroupedArgs{};
             items = 0;
             return e;
         };
         for (int i : order) {
             const lupp_group &g = groups[i];
-            if ((g.n > kRaggedSmallMax) != large) continue;
+            if (ragged_class_of(g.n) != cls) continue;
             const int T = lanes[g.n];
             const int64_t per = grouped_per_item(T);
             /* a group larger than one launch's items is split into ranges */

@@ -3,10 +3,12 @@
  *
  * Systems are grouped by size on the device: a histogram, a plan that lays
  * the size bins out in descending n (costliest work first) and cuts each bin
- * into work items, and a scatter of system indices into the bins. The solve
- * is then either two persistent launches (sizes 17..32, then 1..16) whose
- * workgroups pull work items from an atomic counter and dispatch on n, or one
- * launch per size.
+ * into work items of one workgroup round, and a scatter of system indices
+ * into the bins. The solve is then one launch per size class - classes of
+ * sizes with the same register budget, so that each class runs at the
+ * occupancy its largest size allows - whose workgroups walk the class's work
+ * items with a grid stride (no work counter: the plan gives every workgroup
+ * its items), or one launch per size.
  *
  * System s: matrix column-major at A + offA[s] (lda = n[s]), right-hand side
  * and pivots at offset offB[s], info[s].
@@ -24,15 +26,22 @@ namespace lupp {
 constexpr int kRaggedWaves = 4;       /* wave64s per workgroup */
 constexpr int kRaggedThreads = 64 * kRaggedWaves;
 
+/* Size classes of the ragged and grouped kernels, largest sizes first:
+ * 24..32 (16-lane segments, up to 217 VGPRs: 2 waves per SIMD), 17..23
+ * (16-lane segments, 164 VGPRs: 3 waves; with n = 24 in it the class kernel
+ * spilled) and 1..16. */
+constexpr int kRaggedClasses = 3;
+__host__ __device__ constexpr int ragged_class_lo(int c) { return c == 0 ? 24 : (c == 1 ? 17 : 1); }
+__host__ __device__ constexpr int ragged_class_hi(int c) { return c == 0 ? 32 : (c == 1 ? 23 : 16); }
+__host__ __device__ constexpr int ragged_class_of(int n) { return n >= 24 ? 0 : (n >= 17 ? 1 : 2); }
+
 struct RaggedPlan {
     int32_t count[33];      /* systems of each size */
     int32_t bin_start[33];  /* first index of each size in `sorted` */
     int32_t cursor[33];     /* scatter cursors */
     int32_t item_start[33]; /* first work item of each size */
-    int32_t total_items;
-    int32_t large_items;    /* items of sizes 17..32: numbered 0 .. large_items-1 */
-    int32_t next_item;      /* work counter of the large-size persistent launch */
-    int32_t next_small;     /* work counter of the small-size persistent launch */
+    /* work items of class c: class_start[c] .. class_start[c + 1] - 1 */
+    int32_t class_start[kRaggedClasses + 1];
     int32_t bad;            /* systems with n outside 1..32 */
 };
 
@@ -47,26 +56,20 @@ struct RaggedArgs {
     RaggedPlan *plan;
     /* lanes per system for each size (ragged_lanes_ok). Words, not bytes:
      * 4-byte-aligned kernel arguments are read by scalar loads, where a byte
-     * array is loaded into vector registers (and, in the persistent
+     * array is loaded into vector registers (and, in the looping
      * kernels, spilled to scratch memory) */
     int32_t lanes[33];
 };
 
-/* systems one workgroup solves at once with T lanes per system */
+/* systems one workgroup solves at once with T lanes per system: one work
+ * item (measured: four rounds per item ran 2-11% slower than one, the
+ * workgroup's next loads then waiting for its previous solve) */
 __host__ __device__ constexpr int ragged_per_round(int T)
 {
     return T == 1 ? kRaggedThreads : kRaggedWaves * (64 / T);
 }
 
-/* rounds per work item: items large enough to amortise taking one from the
- * queue, small enough to balance the load across the GPU */
-constexpr int kRaggedRounds = 4;
-
-/* systems handled by one workgroup for one work item */
-__host__ __device__ constexpr int ragged_per_item(int T)
-{
-    return kRaggedRounds * ragged_per_round(T);
-}
+__host__ __device__ constexpr int ragged_per_item(int T) { return ragged_per_round(T); }
 
 /* Where the j-th system of a work item lives: matrix (column-major, leading
  * dimension lda()), right-hand side, pivots and info. */
@@ -196,12 +199,8 @@ template <int N, int T>
 __device__ __forceinline__ void ragged_run_item_t(const RaggedArgs &a, int it)
 {
     const int first = (it - a.plan->item_start[N]) * ragged_per_item(T);
-    for (int r = 0; r < kRaggedRounds; ++r) {
-        const int f = first + r * ragged_per_round(T);
-        const int rest = a.plan->count[N] - f;
-        if (rest <= 0) break;
-        ragged_item<N, T>(a, f, rest < ragged_per_round(T) ? rest : ragged_per_round(T));
-    }
+    const int rest = a.plan->count[N] - first;
+    if (rest > 0) ragged_item<N, T>(a, first, rest < ragged_per_item(T) ? rest : ragged_per_item(T));
 }
 
 template <int N, int T>
@@ -221,17 +220,22 @@ __device__ __forceinline__ bool ragged_try_lanes(const RaggedArgs &a, int lanes,
 template <int N>
 __device__ __forceinline__ void ragged_run_item(const RaggedArgs &a, int it)
 {
-    const int lanes = __builtin_amdgcn_readfirstlane((int)a.lanes[N]);
-    (void)(ragged_try_lanes<N, 1>(a, lanes, it) || ragged_try_lanes<N, 2>(a, lanes, it) ||
-           ragged_try_lanes<N, 4>(a, lanes, it) || ragged_try_lanes<N, 8>(a, lanes, it) ||
-           ragged_try_lanes<N, 16>(a, lanes, it) || ragged_try_lanes<N, 32>(a, lanes, it));
+    if constexpr (N > kRaggedSmallMax) {
+        /* 16 lanes: the only count compiled for these sizes (ragged_lanes_ok) */
+        ragged_run_item_t<N, 16>(a, it);
+    } else {
+        const int lanes = __builtin_amdgcn_readfirstlane((int)a.lanes[N]);
+        (void)(ragged_try_lanes<N, 1>(a, lanes, it) || ragged_try_lanes<N, 2>(a, lanes, it) ||
+               ragged_try_lanes<N, 4>(a, lanes, it) || ragged_try_lanes<N, 8>(a, lanes, it) ||
+               ragged_try_lanes<N, 16>(a, lanes, it));
+    }
 }
 
 /* One size per launch: workgroup b solves work item b of size N. */
 template <int N>
 __global__ void __launch_bounds__(kRaggedThreads) k_ragged_one(RaggedArgs a)
 {
-    const int it = a.plan->item_start[N] + (int)blockIdx.x;
+    const int it = a.plan->item_start[N] + (int)xcd_block(blockIdx.x, gridDim.x);
     ragged_run_item<N>(a, it);
 }
 
@@ -250,29 +254,23 @@ __device__ __forceinline__ void ragged_dispatch(const RaggedArgs &a, int n, int 
     (void)(ragged_try<LO + Ns>(a, n, it) || ...);
 }
 
-/* Persistent loop over the work items [first, end) of sizes LO..HI:
- * workgroups take items (largest sizes first) from the atomic `counter`
- * until every item is taken; every wave leaves the loop on the same
- * broadcast item index. */
-template <int LO, int HI>
-__device__ __forceinline__ void ragged_persistent_loop(const RaggedArgs &a, int32_t *counter, int end)
+/* The work items of class C (sizes LO..HI): workgroup w of a grid of G
+ * takes items class_start[C] + w, + w + G, ... (w remapped so that the
+ * workgroups of one XCD take neighbouring items). Items come largest size
+ * first and every workgroup gets the same mix, so the grid finishes within
+ * about one item of its mean. The size of an item is the smallest m whose
+ * first item is at or before it (empty sizes start where the next one does). */
+template <int C>
+__device__ __forceinline__ void ragged_class_loop(const RaggedArgs &a)
 {
-    __shared__ int sh_item;
+    constexpr int LO = ragged_class_lo(C), HI = ragged_class_hi(C);
     const RaggedPlan *plan = a.plan;
-    for (;;) {
-        if (threadIdx.x == 0) sh_item = atomicAdd(counter, 1);
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(sh_item);
-        __syncthreads();
-        if (it >= end) break;
-        int n = LO;
-        for (int m = LO; m <= HI; ++m) {
-            const int c = plan->count[m];
-            const int per = ragged_per_item(a.lanes[m]);
-            const int nitems = (c + per - 1) / per;
-            const int st = plan->item_start[m];
-            if (it >= st && it < st + nitems) n = m;
-        }
+    const int end = plan->class_start[C + 1];
+    const int G = (int)gridDim.x;
+    for (int it = plan->class_start[C] + (int)xcd_block(blockIdx.x, gridDim.x); it < end; it += G) {
+        int n = HI;
+        for (int m = HI - 1; m >= LO; --m)
+            if (plan->item_start[m] <= it) n = m;
         n = __builtin_amdgcn_readfirstlane(n);
         ragged_dispatch<LO>(a, n, it, std::make_integer_sequence<int, HI - LO + 1>{});
     }
@@ -338,12 +336,16 @@ template <int N>
 __device__ __forceinline__ bool grouped_try(const GroupDesc &g, int n, int local, int factors)
 {
     if (n != N) return false;
-    const int lanes = __builtin_amdgcn_readfirstlane(g.lanes);
-    (void)(grouped_try_lanes<N, 1>(g, lanes, local, factors) ||
-           grouped_try_lanes<N, 2>(g, lanes, local, factors) ||
-           grouped_try_lanes<N, 4>(g, lanes, local, factors) ||
-           grouped_try_lanes<N, 8>(g, lanes, local, factors) ||
-           grouped_try_lanes<N, 16>(g, lanes, local, factors));
+    if constexpr (N > kRaggedSmallMax) {
+        (void)grouped_try_lanes<N, 16>(g, 16, local, factors); /* the only count compiled */
+    } else {
+        const int lanes = __builtin_amdgcn_readfirstlane(g.lanes);
+        (void)(grouped_try_lanes<N, 1>(g, lanes, local, factors) ||
+               grouped_try_lanes<N, 2>(g, lanes, local, factors) ||
+               grouped_try_lanes<N, 4>(g, lanes, local, factors) ||
+               grouped_try_lanes<N, 8>(g, lanes, local, factors) ||
+               grouped_try_lanes<N, 16>(g, lanes, local, factors));
+    }
     return true;
 }
 
@@ -368,15 +370,20 @@ __device__ __forceinline__ void grouped_run(const GroupedArgs &a, int it)
                          std::make_integer_sequence<int, HI - LO + 1>{});
 }
 
-/* The grouped kernels (grouped_large.hip, grouped_small.hip): one workgroup
- * per work item. */
-hipError_t grouped_large_launch(const GroupedArgs &a, unsigned items, hipStream_t st);
-hipError_t grouped_small_launch(const GroupedArgs &a, unsigned items, hipStream_t st);
+/* Grouped kernels (grouped_c0.hip .. grouped_c2.hip), one per size class:
+ * one workgroup per work item. */
+hipError_t grouped_c0_launch(const GroupedArgs &a, unsigned items, hipStream_t st);
+hipError_t grouped_c1_launch(const GroupedArgs &a, unsigned items, hipStream_t st);
+hipError_t grouped_c2_launch(const GroupedArgs &a, unsigned items, hipStream_t st);
 
-/* The two persistent kernels (ragged_large.hip, ragged_small.hip: separate
- * translation units, compiled in parallel): `grid` workgroups each. */
-hipError_t ragged_large_launch(const RaggedArgs &a, unsigned grid, hipStream_t st);
-hipError_t ragged_small_launch(const RaggedArgs &a, unsigned grid, hipStream_t st);
+/* Ragged kernels (ragged_c0.hip .. ragged_c2.hip: separate translation units,
+ * compiled in parallel), one per size class: `grid` workgroups each. */
+hipError_t ragged_c0_launch(const RaggedArgs &a, unsigned grid, hipStream_t st);
+hipError_t ragged_c1_launch(const RaggedArgs &a, unsigned grid, hipStream_t st);
+hipError_t ragged_c2_launch(const RaggedArgs &a, unsigned grid, hipStream_t st);
+/* waves per SIMD each ragged class kernel is compiled for (its resident
+ * grid is compute units x this) */
+__host__ __device__ constexpr int ragged_class_waves(int c) { return c == 0 ? 2 : 3; }
 
 }  // namespace lupp
 

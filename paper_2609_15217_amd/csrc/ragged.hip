@@ -1,5 +1,5 @@
-/* Ragged (mixed-size) batches: device-side grouping by size and two
- * persistent launches, one per size class (see kernels_ragged.h). */
+/* Ragged (mixed-size) batches: device-side grouping by size and one launch
+ * per size class (see kernels_ragged.h). */
 #include <cstring>
 
 #include "kernels_ragged.h"
@@ -44,13 +44,14 @@ __global__ void __launch_bounds__(256) k_ragged_hist(RaggedArgs a)
 }
 
 /* bins in descending size, work items per bin (their size follows the lane
- * count of the size) */
+ * count of the size), class boundaries */
 __global__ void k_ragged_plan(RaggedArgs a)
 {
     if (threadIdx.x != 0) return;
     RaggedPlan *plan = a.plan;
     int start = 0, items = 0;
     for (int n = 32; n >= 1; --n) {
+        if (n == ragged_class_hi(ragged_class_of(n))) plan->class_start[ragged_class_of(n)] = items;
         plan->bin_start[n] = start;
         plan->item_start[n] = items;
         plan->cursor[n] = 0;
@@ -58,11 +59,8 @@ __global__ void k_ragged_plan(RaggedArgs a)
         const int per = ragged_per_item(a.lanes[n]);
         start += c;
         items += (c + per - 1) / per;
-        if (n == kRaggedSmallMax + 1) plan->large_items = items;
     }
-    plan->total_items = items;
-    plan->next_item = 0;
-    plan->next_small = plan->large_items;
+    plan->class_start[kRaggedClasses] = items;
 }
 
 /* scatter system indices into their bins: each workgroup counts its chunk,
@@ -102,7 +100,7 @@ hipError_t ragged_one_launch(int n, const RaggedArgs &a, int items, hipStream_t 
 /* Workspace of the allocating entry point. Calls on one context may come on
  * different streams: `done` is recorded after each call's last kernel, and
  * the next call on another stream waits for it before its grouping kernels
- * reset the plan and rewrite `sorted` (which the earlier call's persistent
+ * reset the plan and rewrite `sorted` (which the earlier call's solve
  * kernels may still be reading). */
 struct RaggedWs {
     RaggedPlan *plan = nullptr;
@@ -146,11 +144,11 @@ int ragged_enqueue(RaggedPlan *plan, int32_t *sorted, const uint8_t *lanes, int6
         int dev = 0, cus = 256;
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        /* as many workgroups as stay resident: a CU holds 4 SIMDs x (waves per
-         * SIMD) waves, 4 waves per workgroup (large: 2 waves per SIMD, small:
-         * 3) */
-        e = ragged_large_launch(a, (unsigned)(cus * 2), st);
-        if (e == hipSuccess) e = ragged_small_launch(a, (unsigned)(cus * 3), st);
+        /* each class kernel with as many workgroups as stay resident: a CU
+         * holds 4 SIMDs x (waves per SIMD) waves, 4 waves per workgroup */
+        e = ragged_c0_launch(a, (unsigned)(cus * ragged_class_waves(0)), st);
+        if (e == hipSuccess) e = ragged_c1_launch(a, (unsigned)(cus * ragged_class_waves(1)), st);
+        if (e == hipSuccess) e = ragged_c2_launch(a, (unsigned)(cus * ragged_class_waves(2)), st);
         return hip_err(e);
     }
     /* one launch per size: the host reads the plan (a synchronisation) */

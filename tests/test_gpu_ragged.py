@@ -1,7 +1,7 @@
 """GPU parity of mixed-size (ragged) batches against the CPU oracle.
 
-Both schedules (one persistent launch over all sizes, and one launch per
-size) must reproduce the oracle's pivots, info, factors and solutions bit for
+Both schedules (one launch per size class, and one launch per size) must
+reproduce the oracle's pivots, info, factors and solutions bit for
 bit, whatever the mix of sizes.
 """
 import numpy as np
@@ -96,8 +96,8 @@ def test_empty_and_arguments(L, ctx):
 
 @pytest.mark.slow
 def test_full_size_mixed_batch_sampled(L, ctx):
-    """2,000,000 systems, n ~ U{2..32}, kappa_2 <= 1e4, the persistent launch
-    as the benchmark times it; 3000 sampled systems compared bitwise."""
+    """2,000,000 systems, n ~ U{2..32}, kappa_2 <= 1e4, the class launches
+    as the benchmark times them; 3000 sampled systems compared bitwise."""
     mx = mixed_systems(2_000_000, seed=3)
     got = run(L, ctx, mx)
     assert np.all(got["info"] == 0)
