@@ -292,7 +292,9 @@ int lupp_variant_info(int n, int layout, int variant, int lanes, int keep_a,
  * F_e = d_eel + dp N - deps; F_p = dp - dt A seq^m; F_a = d_alpha - dp N +
  * D dp alpha.  The start is x = 0. At each iterate: a non-finite residual
  * stops with status 3; ||F||_inf < tol stops with status 0; after maxit linear
- * solves status 1; a zero pivot status 2.
+ * solves status 1; a zero pivot status 2. The linear solves use the FMA mode
+ * of lupp_batched_solve (LUPP_FMA) with textbook pivoting, and the law
+ * multiplies by 1/seq and 1/3 where the formulas divide.
  *
  * Consistent tangent (Section 2.5; Section 4.3: one multi-right-hand-side
  * solve after convergence), when pts->tangent is not NULL: with F(y; deps) =
@@ -353,6 +355,9 @@ int lupp_get_newton_variant(const lupp_ctx *ctx, int kind, int *lanes);
  *   flags      : 0, or LUPP_BATCHED_GRAPH to capture one iteration in a HIP
  *                graph and replay it (one launch per iteration).
  *   iterations : NULL, or receives the number of host-driven iterations.
+ * The batched solves run in the FMA mode (LUPP_FMA), the arithmetic of the
+ * fused kernel's Newton steps, with textbook pivoting: a context set to
+ * tile-local pivoting returns LUPP_E_UNSUPPORTED.
  * Returns as constitutive_update, or -6 for unknown flags. */
 #define LUPP_BATCHED_GRAPH 1u
 int constitutive_update_batched(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law,

@@ -240,7 +240,7 @@ __device__ __forceinline__ void thread_ipiv_to_perm(const int (&ipiv)[N], int (&
  * eliminate the column above, descending) - the operation order of the
  * one-right-hand-side solve. Used for multi-right-hand-side solves with unit
  * vectors, such as a consistent tangent operator. */
-template <int N>
+template <int N, bool kFMA = false>
 __device__ __forceinline__ void thread_solve_unit(const double (&lu)[N][N], const int (&perm)[N],
                                                   int c, double (&x)[N])
 {
@@ -252,7 +252,7 @@ __device__ __forceinline__ void thread_solve_unit(const double (&lu)[N][N], cons
         constexpr int j = decltype(jc)::value;
         static_for<j + 1, N>(LUPP_SF(ic) {
             constexpr int i = decltype(ic)::value;
-            x[i] = x[i] - lu[j][i] * x[j];
+            x[i] = msub<kFMA>(x[i], lu[j][i], x[j]);
         });
     });
     static_for_down<0, N>(LUPP_SF(jc) {
@@ -260,7 +260,7 @@ __device__ __forceinline__ void thread_solve_unit(const double (&lu)[N][N], cons
         x[j] = x[j] / lu[j][j];
         static_for<0, j>(LUPP_SF(ic) {
             constexpr int i = decltype(ic)::value;
-            x[i] = x[i] - lu[j][i] * x[j];
+            x[i] = msub<kFMA>(x[i], lu[j][i], x[j]);
         });
     });
 }

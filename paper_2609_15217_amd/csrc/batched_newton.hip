@@ -207,7 +207,7 @@ static hipError_t bn_iteration(lupp_ctx *ctx, const lupp_points &pts, const LawK
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     *rc = lupp_batched_solve(ctx, NU, pts.count, LUPP_SOA, w.J, NU, pts.count, w.rhs, pts.count,
-                             ws.ipiv, w.info, LUPP_KEEP_A, st);
+                             ws.ipiv, w.info, LUPP_KEEP_A | (kNewtonFMA ? LUPP_FMA : 0u), st);
     if (*rc != 0) return hipSuccess;
     hipLaunchKernelGGL((k_bn_update<NU>), dim3(blocks), dim3(256), 0, st, pts, w);
     e = hipGetLastError();

@@ -19,6 +19,17 @@
 
 namespace lupp {
 
+/* Arithmetic of the Newton updates' linear solves (the Newton step and the
+ * tangent): one fused multiply-add per multiply-subtract, the library's FMA
+ * mode (LUPP_FMA: true divisions, the same pivoting). The fused kernels, the
+ * lanes-per-point kernels and the CPU-driven batched form all use it, so they
+ * stay bitwise equal to each other; against the strict oracle the updates
+ * agree within the Newton tolerance. */
+constexpr bool kNewtonFMA = true;
+
+/* 1/3 rounded once: the means of the law multiply by it */
+constexpr double kThird = 1.0 / 3.0;
+
 struct LawK {
     double lam, two_mu, dtA, m, c23, D;
     int mi; /* m when it is an integer in 1..64 (powers by multiplication), else 0 */
@@ -76,7 +87,7 @@ __device__ __forceinline__ void law_common(const LawK &P, const double (&de)[6],
     constexpr bool af = (NU == 13);
     double xi[6];
     law_stress<NU>(P, st, y, C.sig);
-    const double mean = (C.sig[0] + C.sig[1] + C.sig[2]) / 3.0;
+    const double mean = (C.sig[0] + C.sig[1] + C.sig[2]) * kThird;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         xi[i] = C.sig[i] - (i < 3 ? mean : 0.0);
@@ -94,7 +105,7 @@ __device__ __forceinline__ void law_common(const LawK &P, const double (&de)[6],
     const bool pl = seq > 0.0;
     C.inv = pl ? 1.0 / seq : 0.0;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) C.Nv[i] = pl ? 1.5 * xi[i] / seq : 0.0;
+    for (int i = 0; i < 6; ++i) C.Nv[i] = pl ? 1.5 * xi[i] * C.inv : 0.0;
 
     const double dp = y[6];
     double sm1 = 0.0, sm = 0.0;
@@ -107,7 +118,7 @@ __device__ __forceinline__ void law_common(const LawK &P, const double (&de)[6],
         for (int i = 0; i < 6; ++i) C.F[7 + i] = y[7 + i] - dp * C.Nv[i] + P.D * dp * C.al[i];
     }
     C.dp = dp;
-    C.nmean = (C.Nv[0] + C.Nv[1] + C.Nv[2]) / 3.0;
+    C.nmean = (C.Nv[0] + C.Nv[1] + C.Nv[2]) * kThird;
     C.gd = P.dtA * P.m * sm1; /* d(dt A seq^m)/dseq */
     C.dp2mu = dp * P.two_mu;
     C.cdp = P.c23 * dp;
@@ -121,7 +132,7 @@ __device__ __forceinline__ void law_g_row(const double (&Nv)[6], double inv, int
 {
 #pragma unroll
     for (int b = 0; b < 6; ++b) G[b] = ((a == b ? 1.5 : 0.0) - Na * Nv[b]) * inv;
-    const double rowmean = (G[0] + G[1] + G[2]) / 3.0;
+    const double rowmean = (G[0] + G[1] + G[2]) * kThird;
 #pragma unroll
     for (int b = 0; b < 6; ++b) GK[b] = G[b] - (b < 3 ? rowmean : 0.0);
 }
@@ -261,12 +272,12 @@ __device__ __forceinline__ void newton_tangent7(const LawK &P, const double (&de
     law_assemble<7>(P, de, st, y, Fc, J, sc);
 #pragma unroll
     for (int i = 0; i < 7; ++i) z[i] = 0.0;
-    const bool sing = thread_getrf_solve<7, true>(J, z, piv) != 0;
+    const bool sing = thread_getrf_solve<7, true, kNewtonFMA>(J, z, piv) != 0;
     thread_ipiv_to_perm<7>(piv, perm);
 #pragma unroll 1
     for (int c = 0; c < 6; ++c) {
         double x[7];
-        thread_solve_unit<7>(J, perm, c, x);
+        thread_solve_unit<7, kNewtonFMA>(J, perm, c, x);
         tangent_store_col<7>(P, pts, p0, nb, vo, c, x, sing);
     }
 }
@@ -292,7 +303,7 @@ static __device__ __forceinline__ void newton_tangent13(const LawK &P, const dou
         law_assemble<13>(P, de, st, y, Fc, J, sc);
 #pragma unroll
         for (int i = 0; i < 13; ++i) x[i] = (i == c) ? 1.0 : 0.0;
-        const bool sing = thread_getrf_solve<13, false>(J, x, piv) != 0;
+        const bool sing = thread_getrf_solve<13, false, kNewtonFMA>(J, x, piv) != 0;
         tangent_store_col<13>(P, pts, p0, nb, vo, c, x, sing);
     }
 }

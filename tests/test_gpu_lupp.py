@@ -5,6 +5,8 @@ bit for bit (strict mode: same pivot choices, same rounded operations per
 element, no FMA), for every compiled variant, both layouts, ragged batch
 tails, strides and degenerate inputs.
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -214,30 +216,67 @@ def test_config1_default_dispatch(L, ctx):
         assert_same(ref, LU, x, pv, io)
 
 
+def bench_soa_ld():
+    """The interleaved ldbatch the benchmark lays its arrays out with."""
+    import importlib.util
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_consts", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    return bench.SOA_LD
+
+
+@functools.lru_cache(maxsize=1)
+def full_size_systems(n):
+    return systems(n, 1 << 20, seed=2000 + n, kappa_max=1e4)
+
+
 @pytest.mark.slow
+@pytest.mark.parametrize("layout", ["soa", "aos"])
 @pytest.mark.parametrize("n", [4, 8, 12, 16, 24, 32])
-def test_full_size_sweep_sampled(L, ctx, n):
-    """2^20 systems per size (kappa_2 <= 1e4), SoA, default dispatch as the
-    benchmark launches it; 4096 sampled systems compared bitwise."""
+def test_full_size_sweep_sampled(L, ctx, n, layout):
+    """2^20 systems per size (kappa_2 <= 1e4), default dispatch, in the
+    benchmark's launch configuration (interleaved arrays with its padded
+    ldbatch, or packed AoS); 4096 sampled systems compared bitwise."""
     batch = 1 << 20
-    A, b, xt = systems(n, batch, seed=2000 + n, kappa_max=1e4)
+    A, b, xt = full_size_systems(n)
     dev = torch.device("cuda:0")
-    tA = torch.from_numpy(aos_to_soa(A)).to(dev)
-    tb = torch.from_numpy(aos_to_soa(b)).to(dev)
-    ipiv, info = L.batched_solve(ctx, tA, tb, L.LUPP_SOA)
+    info = torch.full((batch,), -7, dtype=torch.int32, device=dev)
+    if layout == "soa":
+        ld = bench_soa_ld()
+        tA = torch.zeros((n, n, ld), dtype=torch.float64, device=dev)
+        tA[:, :, :batch] = torch.from_numpy(aos_to_soa(A)).to(dev)
+        tb = torch.zeros((n, ld), dtype=torch.float64, device=dev)
+        tb[:, :batch] = torch.from_numpy(aos_to_soa(b)).to(dev)
+        ipiv = torch.zeros((n, ld), dtype=torch.int32, device=dev)
+        rc = L.lupp_batched_solve(ctx, n, batch, L.LUPP_SOA, tA, n, ld, tb, ld, ipiv, info)
+    else:
+        tA = torch.from_numpy(A).to(dev)
+        tb = torch.from_numpy(b).to(dev)
+        ipiv = torch.zeros((batch, n), dtype=torch.int32, device=dev)
+        rc = L.lupp_batched_solve(ctx, n, batch, L.LUPP_AOS, tA, n, n * n, tb, n, ipiv, info)
+    assert rc == 0, L.lupp_error_string(rc)
     torch.cuda.synchronize()
     rng = np.random.Generator(np.random.PCG64(n))
     idx = np.sort(rng.choice(batch, 4096, replace=False))
     idx[-1] = batch - 1
     ref = oracle.gesv_batch(A[idx], b[idx], threads=8)
-    x = tb.cpu().numpy()[:, idx].T
-    LU = tA.cpu().numpy()[:, :, idx].transpose(2, 0, 1)
+    if layout == "soa":
+        xa = tb[:, :batch].cpu().numpy().T
+        LU = tA[:, :, :batch].cpu().numpy()[:, :, idx].transpose(2, 0, 1)
+        pv = ipiv[:, :batch].cpu().numpy()[:, idx].T
+        assert not tA[:, :, batch:].any() and not tb[:, batch:].any()  # padding untouched
+    else:
+        xa = tb.cpu().numpy()
+        LU = tA.cpu().numpy()[idx]
+        pv = ipiv.cpu().numpy()[idx]
     assert np.array_equal(info.cpu().numpy(), np.zeros(batch, dtype=np.int32))
-    assert np.array_equal(ipiv.cpu().numpy()[:, idx].T, ref["ipiv"])
+    assert np.array_equal(pv, ref["ipiv"])
     assert np.array_equal(LU, ref["LU"])
-    assert np.array_equal(x, ref["x"])
+    assert np.array_equal(xa[idx], ref["x"])
     # forward error against the known solution (kappa_2 <= 1e4)
-    fe = np.abs(tb.cpu().numpy().T - xt).max(axis=1) / np.abs(xt).max(axis=1)
+    fe = np.abs(xa - xt).max(axis=1) / np.abs(xt).max(axis=1)
     assert fe.max() < 1e-9
 
 
