@@ -293,8 +293,10 @@ int lupp_variant_info(int n, int layout, int variant, int lanes, int keep_a,
  * D dp alpha.  The start is x = 0. At each iterate: a non-finite residual
  * stops with status 3; ||F||_inf < tol stops with status 0; after maxit linear
  * solves status 1; a zero pivot status 2. The linear solves use the FMA mode
- * of lupp_batched_solve (LUPP_FMA) with textbook pivoting, and the law
- * multiplies by 1/seq and 1/3 where the formulas divide.
+ * of lupp_batched_solve (LUPP_FMA) with textbook pivoting and one division
+ * per elimination step (multipliers and back substitution by the pivot's
+ * reciprocal), and the law multiplies by 1/seq and 1/3 where the formulas
+ * divide.
  *
  * Consistent tangent (Section 2.5; Section 4.3: one multi-right-hand-side
  * solve after convergence), when pts->tangent is not NULL: with F(y; deps) =
@@ -344,21 +346,20 @@ int lupp_get_newton_variant(const lupp_ctx *ctx, int kind, int *lanes);
 
 /* CPU-driven batched form of the same update (Algorithm 1; Section 2.5),
  * for comparison with the fused kernel: each Newton iteration is an assemble
- * launch over all points, one batched LU solve of all Jacobians
- * (lupp_batched_solve, interleaved layout) and an update launch, after which
+ * launch over all points, one batched LU solve launch over all Jacobians
+ * (interleaved layout) and an update launch, after which
  * the host reads one counter of points still iterating. Finished points are
  * carried through the remaining batched solves but do not change, so every
  * output (sig, state, iters, status, tangent) is bitwise the one
  * constitutive_update computes. Blocks the calling thread until done (it
  * synchronises `stream` once per iteration). The context keeps the device
- * workspace (about 8 (kind^2 + 2 kind + 4) bytes per point) between calls.
+ * workspace (about 8 (kind^2 + kind + 3) bytes per point) between calls.
  *   flags      : 0, or LUPP_BATCHED_GRAPH to capture one iteration in a HIP
  *                graph and replay it (one launch per iteration).
  *   iterations : NULL, or receives the number of host-driven iterations.
- * The batched solves run in the FMA mode (LUPP_FMA), the arithmetic of the
- * fused kernel's Newton steps, with textbook pivoting: a context set to
- * tile-local pivoting returns LUPP_E_UNSUPPORTED.
- * Returns as constitutive_update, or -6 for unknown flags. */
+ * The batched solve is the library's thread solver in the arithmetic of the
+ * fused kernel's Newton steps (textbook pivoting whatever the context's
+ * setting). Returns as constitutive_update, or -6 for unknown flags. */
 #define LUPP_BATCHED_GRAPH 1u
 int constitutive_update_batched(lupp_ctx *ctx, const lupp_points *pts, const lupp_law *law,
                                 double tol, int maxit, unsigned flags, void *stream,

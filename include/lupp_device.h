@@ -115,12 +115,19 @@ __device__ __forceinline__ int pivot_tile_end(int k, int n, int tile)
  * bound how far the compiler interleaves the swaps: measured on gfx950 this
  * form needs far fewer registers than selecting the pivot row out of all
  * candidates column by column (n = 8: 170 VGPRs against 256 plus scratch;
- * n = 13: no scratch against 1204 bytes per lane). */
-template <int N, bool kFactors, bool kFMA = false, bool kTile = false>
+ * n = 13: no scratch against 1204 bytes per lane).
+ *
+ * kRecip (solve only, kFactors false): one division per step - the pivot's
+ * reciprocal - by which the multipliers are formed and, stored in the
+ * pivot's place, the back substitution multiplies: 13 divisions instead of
+ * 91 at n = 13. The rounding differs from the true divisions of the default
+ * (and of the oracle). */
+template <int N, bool kFactors, bool kFMA = false, bool kTile = false, bool kRecip = false>
 __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)[N],
                                                   int (&ipiv)[N], int tile = 0,
                                                   double thresh = 0.0)
 {
+    static_assert(!(kRecip && kFactors), "the reciprocal form overwrites the pivots");
     int info = 0;
     static_for<0, N>(LUPP_SF(kc) {
         constexpr int k = decltype(kc)::value;
@@ -180,10 +187,22 @@ __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)
 
         if (!zero) {
             /* multipliers, Schur-complement update, forward substitution */
-            static_for<k + 1, N>(LUPP_SF(ic) {
-                constexpr int i = decltype(ic)::value;
-                a[k][i] = a[k][i] / pv;
-            });
+            if constexpr (kRecip) {
+                /* one division per step: the multipliers take the pivot's
+                 * reciprocal, which then replaces the pivot for the back
+                 * substitution */
+                const double r = 1.0 / pv;
+                static_for<k + 1, N>(LUPP_SF(ic) {
+                    constexpr int i = decltype(ic)::value;
+                    a[k][i] = a[k][i] * r;
+                });
+                a[k][k] = r;
+            } else {
+                static_for<k + 1, N>(LUPP_SF(ic) {
+                    constexpr int i = decltype(ic)::value;
+                    a[k][i] = a[k][i] / pv;
+                });
+            }
             static_for<k + 1, N>(LUPP_SF(jc) {
                 constexpr int j = decltype(jc)::value;
                 static_for<k + 1, N>(LUPP_SF(ic) {
@@ -200,7 +219,8 @@ __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)
     if (info == 0) {
         static_for_down<0, N>(LUPP_SF(jc) {
             constexpr int j = decltype(jc)::value;
-            b[j] = b[j] / a[j][j];
+            if constexpr (kRecip) b[j] = b[j] * a[j][j];
+            else b[j] = b[j] / a[j][j];
             static_for<0, j>(LUPP_SF(ic) {
                 constexpr int i = decltype(ic)::value;
                 b[i] = msub<kFMA>(b[i], a[j][i], b[j]);
@@ -446,7 +466,7 @@ __device__ __forceinline__ int lanes_pivot_owner(const double (&a)[(N + T - 1) /
  * lane of the segment sees every x_j: x_sink(j, x_j) is called by all lanes
  * (a solver whose callers need the whole solution in every lane gets it
  * without further communication). */
-template <int N, int T, bool kFMA, typename XSink>
+template <int N, int T, bool kFMA, bool kRecip, typename XSink>
 __device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) / T][N],
                                                  double (&b)[(N + T - 1) / T],
                                                  const int (&pos)[(N + T - 1) / T], int seg_base,
@@ -465,7 +485,8 @@ __device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) /
             bs = hit ? b[s] : bs;
             us = hit ? a[s][j] : us;
         });
-        const double xl = bs / us;
+        /* kRecip: the row holds the pivot's reciprocal in place of u_jj */
+        const double xl = kRecip ? bs * us : bs / us;
         const unsigned ob = (unsigned)(__ballot(mine) >> (unsigned)seg_base) & lowmask;
         const int owner = seg_base + (int)__builtin_ctz(ob | (1u << 31));
         const double x = bcast_f64(xl, owner);
@@ -493,9 +514,12 @@ __device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) /
  * select the pivoting rule (see thread_getrf_solve). CH is the number of
  * pivot-row columns broadcast (and held in registers) at a time within a
  * step: larger chunks expose more independent broadcasts per wait at the
- * cost of 2*CH VGPRs. Results do not depend on it. */
-template <int N, int T, bool kFMA = false, bool kTile = false, int CH = 8, typename IpivSink,
-          typename XSink>
+ * cost of 2*CH VGPRs. Results do not depend on it. kRecip: one division per
+ * step (the pivot's reciprocal, by which the multipliers are formed and the
+ * back substitution multiplies) instead of one per multiplier, as
+ * thread_getrf_solve with kRecip; the factors are then not LAPACK's. */
+template <int N, int T, bool kFMA = false, bool kTile = false, int CH = 8, bool kRecip = false,
+          typename IpivSink, typename XSink>
 __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][N],
                                                    double (&b)[(N + T - 1) / T],
                                                    int (&pos)[(N + T - 1) / T], int seg_base,
@@ -544,11 +568,20 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
 
         if (!zero) {
             double l[K];
-            static_for<0, K>(LUPP_SF(sc) {
-                constexpr int s = decltype(sc)::value;
-                l[s] = a[s][k] / pv;
-                a[s][k] = trail[s] ? l[s] : a[s][k];
-            });
+            if constexpr (kRecip) {
+                const double r = 1.0 / pv;
+                static_for<0, K>(LUPP_SF(sc) {
+                    constexpr int s = decltype(sc)::value;
+                    l[s] = a[s][k] * r;
+                    a[s][k] = trail[s] ? l[s] : ((own && ls == s) ? r : a[s][k]);
+                });
+            } else {
+                static_for<0, K>(LUPP_SF(sc) {
+                    constexpr int s = decltype(sc)::value;
+                    l[s] = a[s][k] / pv;
+                    a[s][k] = trail[s] ? l[s] : a[s][k];
+                });
+            }
             double ys = b[0];
             static_for<1, K>(LUPP_SF(sc) {
                 constexpr int s = decltype(sc)::value;
@@ -587,7 +620,7 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
             }
         }
     });
-    if (info == 0) lanes_back_subst<N, T, kFMA>(a, b, pos, seg_base, x_sink);
+    if (info == 0) lanes_back_subst<N, T, kFMA, kRecip>(a, b, pos, seg_base, x_sink);
     return info;
 }
 

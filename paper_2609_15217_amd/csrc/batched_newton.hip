@@ -1,19 +1,20 @@
 /* CPU-driven batched Newton constitutive update (Algorithm 1; Section 2.5):
  * every Newton iteration is three launches - assemble F and J for all points,
- * one batched LU solve of all the Jacobians (the library's own
- * lupp_batched_solve), update the unknowns and apply the stop rules - and the
- * host reads one counter after each iteration to decide whether to go on.
- * Points that have finished are carried through the remaining batched solves
- * (the batched paradigm's dragging, Section 2.5) but no longer change, so
- * every point follows exactly the iteration sequence of the fused kernel and
- * the results are bitwise those of constitutive_update.
+ * one batched LU solve of all the Jacobians, update the unknowns and apply the
+ * stop rules - and the host reads one counter after each iteration to decide
+ * whether to go on. The batched solve is the library's register-resident
+ * thread solver over the interleaved Jacobians, in the Newton arithmetic of
+ * law.h (the standalone batched solve has no reciprocal-pivot mode). Points
+ * that have finished are carried through the remaining batched solves (the
+ * batched paradigm's dragging, Section 2.5) but no longer change, so every
+ * point follows exactly the iteration sequence of the fused kernel and the
+ * results are bitwise those of constitutive_update.
  *
  * Workspace (owned by the context, grown on demand), all interleaved (SoA,
- * point index fastest) so that every kernel's accesses are coalesced and the
- * batched solve runs on its SoA path: unknowns y [NU][count], Jacobians
- * [NU*NU][count] (element (r, c) at row r + c*NU), right-hand sides
- * [NU][count], ipiv [NU][count], info, per-point state and the active-point
- * counter.
+ * point index fastest) so that every kernel's accesses are coalesced:
+ * unknowns y [NU][count], Jacobians [NU*NU][count] (element (r, c) at row
+ * r + c*NU), right-hand sides [NU][count], info, per-point state and the
+ * active-point counter.
  */
 #include "law.h"
 
@@ -119,6 +120,31 @@ __global__ void __launch_bounds__(256) k_bn_assemble(lupp_points pts, LawK P, Bn
     if (__lane_id() == 0 && b != 0) atomicAdd(w.active, (int)__builtin_popcountll(b));
 }
 
+/* The batched solve: point p's Jacobian and right-hand side, solved in
+ * registers (J dx = -F, dx overwriting the right-hand side where the
+ * factorisation has no zero pivot), info[p]. */
+template <int NU>
+__global__ void __launch_bounds__(256) k_bn_solve(BnArgs w)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= w.count) return;
+    const int64_t C = w.count;
+    double a[NU][NU], x[NU];
+    int piv[NU];
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+#pragma unroll
+        for (int r = 0; r < NU; ++r) a[c][r] = w.J[(r + c * NU) * C + p];
+        x[c] = w.rhs[c * C + p];
+    }
+    const int inf = thread_getrf_solve<NU, false, kNewtonFMA, false, kNewtonRecip>(a, x, piv);
+    if (inf == 0) {
+#pragma unroll
+        for (int c = 0; c < NU; ++c) w.rhs[c * C + p] = x[c];
+    }
+    w.info[p] = inf;
+}
+
 /* x += dx for the points that iterated; a zero pivot stops a point with
  * status 2 (its iterate is not updated, as in the fused loop). */
 template <int NU>
@@ -141,7 +167,7 @@ struct BnWs {
     int64_t cap = 0;
     int nu = 0;
     double *y = nullptr, *J = nullptr, *rhs = nullptr;
-    int32_t *ipiv = nullptr, *info = nullptr, *st = nullptr, *it = nullptr, *active = nullptr;
+    int32_t *info = nullptr, *st = nullptr, *it = nullptr, *active = nullptr;
     int32_t *host_active = nullptr; /* pinned */
 };
 
@@ -152,13 +178,12 @@ static void bn_ws_release(BnWs *ws)
     hipFree(ws->y);
     hipFree(ws->J);
     hipFree(ws->rhs);
-    hipFree(ws->ipiv);
     hipFree(ws->info);
     hipFree(ws->st);
     hipFree(ws->it);
     hipFree(ws->active);
     ws->y = ws->J = ws->rhs = nullptr;
-    ws->ipiv = ws->info = ws->st = ws->it = ws->active = nullptr;
+    ws->info = ws->st = ws->it = ws->active = nullptr;
     ws->cap = 0;
     ws->nu = 0;
 }
@@ -181,7 +206,6 @@ static hipError_t bn_ws_reserve(BnWs *ws, int64_t count, int nu, hipStream_t st)
     e = hipMalloc(&ws->y, C * nu * 8);
     if (e == hipSuccess) e = hipMalloc(&ws->J, C * nu * nu * 8);
     if (e == hipSuccess) e = hipMalloc(&ws->rhs, C * nu * 8);
-    if (e == hipSuccess) e = hipMalloc(&ws->ipiv, C * nu * 4);
     if (e == hipSuccess) e = hipMalloc(&ws->info, C * 4);
     if (e == hipSuccess) e = hipMalloc(&ws->st, C * 4);
     if (e == hipSuccess) e = hipMalloc(&ws->it, C * 4);
@@ -201,14 +225,17 @@ template <int NU, bool TAN>
 static hipError_t bn_iteration(lupp_ctx *ctx, const lupp_points &pts, const LawK &P, const BnArgs &w,
                                const BnWs &ws, double tol, int maxit, hipStream_t st, int *rc)
 {
+    (void)ctx;
+    (void)ws;
     const unsigned blocks = (unsigned)((pts.count + 255) / 256);
     hipLaunchKernelGGL(k_bn_zero, dim3(1), dim3(64), 0, st, w.active);
     hipLaunchKernelGGL((k_bn_assemble<NU, TAN>), dim3(blocks), dim3(256), 0, st, pts, P, w, tol, maxit);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    *rc = lupp_batched_solve(ctx, NU, pts.count, LUPP_SOA, w.J, NU, pts.count, w.rhs, pts.count,
-                             ws.ipiv, w.info, LUPP_KEEP_A | (kNewtonFMA ? LUPP_FMA : 0u), st);
-    if (*rc != 0) return hipSuccess;
+    hipLaunchKernelGGL((k_bn_solve<NU>), dim3(blocks), dim3(256), 0, st, w);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    *rc = 0;
     hipLaunchKernelGGL((k_bn_update<NU>), dim3(blocks), dim3(256), 0, st, pts, w);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -72,7 +72,10 @@ __device__ __forceinline__ void newton_block(const lupp_points &pts, const LawK 
         int piv[NU];
 #pragma unroll
         for (int i = 0; i < NU; ++i) dx[i] = -F[i];
-        if (thread_getrf_solve<NU, false, kNewtonFMA>(J, dx, piv) != 0) { status = 2; break; }
+        if (thread_getrf_solve<NU, false, kNewtonFMA, false, kNewtonRecip>(J, dx, piv) != 0) {
+            status = 2;
+            break;
+        }
 #pragma unroll
         for (int i = 0; i < NU; ++i) Y(i) = Y(i) + dx[i];
     }
@@ -198,8 +201,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
         });
         /* x += dx as the back substitution hands out each dx_j (a zero pivot
          * skips the substitution, so y is then unchanged) */
-        const int inf = lanes_getrf_solve_x<NU, T, kNewtonFMA>(a, b, pos, g * T, [](int, int) {},
-                                                   [&](int j, double x) { y[j] = y[j] + x; });
+        const int inf = lanes_getrf_solve_x<NU, T, kNewtonFMA, false, 8, kNewtonRecip>(
+            a, b, pos, g * T, [](int, int) {}, [&](int j, double x) { y[j] = y[j] + x; });
         if (inf != 0) { status = 2; break; }
     }
 

@@ -20,12 +20,15 @@
 namespace lupp {
 
 /* Arithmetic of the Newton updates' linear solves (the Newton step and the
- * tangent): one fused multiply-add per multiply-subtract, the library's FMA
- * mode (LUPP_FMA: true divisions, the same pivoting). The fused kernels, the
- * lanes-per-point kernels and the CPU-driven batched form all use it, so they
- * stay bitwise equal to each other; against the strict oracle the updates
- * agree within the Newton tolerance. */
+ * tangent): one fused multiply-add per multiply-subtract (the library's FMA
+ * mode), and one division per elimination step - the multipliers and the
+ * back substitution use the pivot's reciprocal - with textbook pivoting. The
+ * fused kernels, the lanes-per-point kernels and the CPU-driven batched form
+ * all use it, so they stay bitwise equal to each other; against the strict
+ * oracle the updates agree within the Newton tolerance. (The 7-unknown
+ * tangent keeps its factors for six right-hand sides and so divides.) */
 constexpr bool kNewtonFMA = true;
+constexpr bool kNewtonRecip = true;
 
 /* 1/3 rounded once: the means of the law multiply by it */
 constexpr double kThird = 1.0 / 3.0;
@@ -303,7 +306,8 @@ static __device__ __forceinline__ void newton_tangent13(const LawK &P, const dou
         law_assemble<13>(P, de, st, y, Fc, J, sc);
 #pragma unroll
         for (int i = 0; i < 13; ++i) x[i] = (i == c) ? 1.0 : 0.0;
-        const bool sing = thread_getrf_solve<13, false, kNewtonFMA>(J, x, piv) != 0;
+        const bool sing =
+            thread_getrf_solve<13, false, kNewtonFMA, false, kNewtonRecip>(J, x, piv) != 0;
         tangent_store_col<13>(P, pts, p0, nb, vo, c, x, sing);
     }
 }
