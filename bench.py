@@ -800,8 +800,10 @@ def main():
         "cpu_baseline": cpu,
     }
     # Release the device arrays and the library context before the result
-    # line, and leave right after it: the process then has nothing to tear
-    # down (about 100 GB of device memory) once its output is complete.
+    # line: the process then has next to nothing to tear down (about 100 GB
+    # of device memory were held) once its output is complete. (A hard exit
+    # right after the line would also skip the exit handlers a profiler
+    # writes its results from.)
     pristine.clear()
     work.clear()
     host.clear()
@@ -809,8 +811,6 @@ def main():
     ctx.close()
     torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
-    sys.stderr.flush()
-    os._exit(0)
 
 
 if __name__ == "__main__":

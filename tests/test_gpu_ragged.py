@@ -48,7 +48,12 @@ def same(ref, got, keep_a=False, A=None):
 
 @pytest.mark.parametrize("flags", [0, 2])
 @pytest.mark.parametrize("batch,nmin,nmax", [(3001, 2, 32), (777, 1, 8), (1500, 17, 32), (1, 32, 32),
-                                             (600, 13, 13)])
+                                             (600, 13, 13),
+                                             # one size class alone, and the class boundaries
+                                             (900, 17, 23), (900, 24, 32), (1200, 16, 17),
+                                             (1200, 23, 24),
+                                             # several grid-stride rounds in every class
+                                             (100000, 1, 32)])
 def test_mixed_sizes_bitwise(L, ctx, batch, nmin, nmax, flags):
     mx = mixed_systems(batch, seed=300 + batch, nmin=nmin, nmax=nmax, kappa_max=None)
     ref = oracle.gesv_ragged(mx["n"], mx["offA"], mx["offB"], mx["A"], mx["b"], threads=8)
