@@ -98,12 +98,56 @@ __device__ __forceinline__ int pivot_tile_end(int k, int n, int tile)
     return e < n ? e : n;
 }
 
+/* Pivot of column k over rows k .. N-1 (element (i, k) at a[k][i]): the
+ * largest magnitude, the lowest row among equal ones, by a pairwise (tree)
+ * reduction in which the right (higher) half wins only when strictly larger:
+ * the choice of a left-to-right scan for any non-NaN column, with
+ * ceil(log2(N - k)) dependent compare/select levels instead of N - k - 1.
+ * best, pv, p: magnitude, signed value and row of the pivot. */
+template <int N, int k>
+__device__ __forceinline__ void thread_pivot_tree(const double (&a)[N][N], double &best, double &pv,
+                                                  int &p)
+{
+    constexpr int M = N - k;
+    double mg[M], vl[M];
+    int id[M];
+    static_for<0, M>(LUPP_SF(ic) {
+        constexpr int i = decltype(ic)::value;
+        mg[i] = fabs(a[k][k + i]);
+        vl[i] = a[k][k + i];
+        id[i] = k + i;
+    });
+    static_for<0, 6>(LUPP_SF(lc) {
+        constexpr int st = 1 << decltype(lc)::value;
+        if constexpr (st < M) {
+            static_for<0, (M + 2 * st - 1) / (2 * st)>(LUPP_SF(pc) {
+                constexpr int i = decltype(pc)::value * 2 * st;
+                if constexpr (i + st < M) {
+                    const bool gt = mg[i + st] > mg[i];
+                    mg[i] = gt ? mg[i + st] : mg[i];
+                    vl[i] = gt ? vl[i + st] : vl[i];
+                    id[i] = gt ? id[i + st] : id[i];
+                }
+            });
+        }
+    });
+    best = mg[0];
+    pv = vl[0];
+    p = id[0];
+}
+
 /* Pivoting rule (all solvers): textbook partial pivoting unless the kTile
  * parameter is set (then tile >= 1 is required): tile-local pivoting, where
  * the candidates at step k are first the rows k .. pivot_tile_end - 1, and
  * only if the best of them has magnitude below `thresh` are all rows
  * k .. n-1 searched; ties go to the lowest row (position) either way.
  * Without kTile the solvers contain no tile code at all.
+ *
+ * Search shape (thread solver): a running left-to-right scan where the
+ * factors are kept (fewer values live: n = 8 stays free of scratch at three
+ * waves per SIMD), a pairwise tree for solve-only calls such as the Newton
+ * steps (a dependent chain of ceil(log2(n - k)) compare/selects instead of
+ * n - k - 1). Both pick the same row unless the column holds a NaN.
  *
  * Interchange: the pivot row p is data while register indices are not, so
  * rows k and p are swapped by selects, one candidate row i at a time, and
@@ -137,15 +181,19 @@ __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)
         double best = fabs(a[k][k]);
         double pv = a[k][k];
         int p = k;
-        static_for<k + 1, N>(LUPP_SF(ic) {
-            constexpr int i = decltype(ic)::value;
-            const double v = fabs(a[k][i]);
-            bool gt = v > best;
-            if constexpr (kTile) gt = gt & (i < k1);
-            best = gt ? v : best;
-            pv = gt ? a[k][i] : pv;
-            p = gt ? i : p;
-        });
+        if constexpr (!kTile && !kFactors) {
+            thread_pivot_tree<N, k>(a, best, pv, p);
+        } else {
+            static_for<k + 1, N>(LUPP_SF(ic) {
+                constexpr int i = decltype(ic)::value;
+                const double v = fabs(a[k][i]);
+                bool gt = v > best;
+                if constexpr (kTile) gt = gt & (i < k1);
+                best = gt ? v : best;
+                pv = gt ? a[k][i] : pv;
+                p = gt ? i : p;
+            });
+        }
         if (kTile && __ballot(best < thresh) != 0) {
             const bool wide = best < thresh;
             double bw = fabs(a[k][k]);
@@ -166,6 +214,10 @@ __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)
         ipiv[k] = p + 1;
         const bool zero = (pv == 0.0);
         info = (zero && info == 0) ? k + 1 : info;
+        /* kRecip: the reciprocal needs only the pivot value, so its latency
+         * runs under the interchange below (a zero pivot gives an unused
+         * infinity) */
+        const double rp = kRecip ? 1.0 / pv : 0.0;
 
         /* interchange rows k and p: exactly one candidate i matches p in a
          * lane, so the conditional swaps compose to the single interchange */
@@ -191,12 +243,11 @@ __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)
                 /* one division per step: the multipliers take the pivot's
                  * reciprocal, which then replaces the pivot for the back
                  * substitution */
-                const double r = 1.0 / pv;
                 static_for<k + 1, N>(LUPP_SF(ic) {
                     constexpr int i = decltype(ic)::value;
-                    a[k][i] = a[k][i] * r;
+                    a[k][i] = a[k][i] * rp;
                 });
-                a[k][k] = r;
+                a[k][k] = rp;
             } else {
                 static_for<k + 1, N>(LUPP_SF(ic) {
                     constexpr int i = decltype(ic)::value;
