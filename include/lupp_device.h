@@ -78,6 +78,30 @@ __device__ __forceinline__ void static_for_down(F &&f)
 
 #define LUPP_SF(v) [&](auto v) __attribute__((always_inline))
 
+/* Register-lifetime fence: an empty asm statement that takes x and hands it
+ * back, so whatever produces x is computed at this point. The solvers fence
+ * values that are final long before their only use (a stored multiplier, the
+ * running info, an interchange index kept for the store): left alone, the
+ * compiler may keep every step's operands live and form such values at the
+ * use, which costs registers (16 lanes per system at n = 32: 195 VGPRs, two
+ * waves per SIMD, against 168 and three). No instruction is emitted and no
+ * result changes. */
+template <typename V>
+__device__ __forceinline__ void settle(V &x)
+{
+    asm volatile("" : "+v"(x));
+}
+
+/* Whether the batched lanes kernels fence the solver's per-step results:
+ * where the unfenced kernel needs more than 168 VGPRs (16 lanes per system
+ * from n = 27) and the fence buys a third wave per SIMD. Elsewhere it would
+ * only hold the scheduler back (n = 24 on 16 lanes: 3.06 -> 3.23 ms). */
+template <int N, int T>
+constexpr bool lanes_settle()
+{
+    return T == 16 && N >= 27;
+}
+
 /* a - l*u: in strict mode one rounded multiply then one rounded subtract;
  * with kFMA one fused multiply-add (fma(-l, u, a), a single rounding). */
 template <bool kFMA>
@@ -570,7 +594,7 @@ __device__ __forceinline__ void lanes_back_subst(const double (&a)[(N + T - 1) /
  * back substitution multiplies) instead of one per multiplier, as
  * thread_getrf_solve with kRecip; the factors are then not LAPACK's. */
 template <int N, int T, bool kFMA = false, bool kTile = false, int CH = 8, bool kRecip = false,
-          typename IpivSink, typename XSink>
+          bool kSettle = false, typename IpivSink, typename XSink>
 __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][N],
                                                    double (&b)[(N + T - 1) / T],
                                                    int (&pos)[(N + T - 1) / T], int seg_base,
@@ -616,6 +640,7 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
         });
         const bool zero = (M == 0.0);
         info = (zero && info == 0) ? k + 1 : info;
+        if constexpr (kSettle) settle(info);
 
         if (!zero) {
             double l[K];
@@ -625,12 +650,14 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
                     constexpr int s = decltype(sc)::value;
                     l[s] = a[s][k] * r;
                     a[s][k] = trail[s] ? l[s] : ((own && ls == s) ? r : a[s][k]);
+                    if constexpr (kSettle) settle(a[s][k]);
                 });
             } else {
                 static_for<0, K>(LUPP_SF(sc) {
                     constexpr int s = decltype(sc)::value;
                     l[s] = a[s][k] / pv;
                     a[s][k] = trail[s] ? l[s] : a[s][k];
+                    if constexpr (kSettle) settle(a[s][k]);
                 });
             }
             double ys = b[0];
@@ -675,13 +702,14 @@ __device__ __forceinline__ int lanes_getrf_solve_x(double (&a)[(N + T - 1) / T][
     return info;
 }
 
-template <int N, int T, bool kFMA = false, bool kTile = false, int CH = 8, typename IpivSink>
+template <int N, int T, bool kFMA = false, bool kTile = false, int CH = 8, bool kSettle = false,
+          typename IpivSink>
 __device__ __forceinline__ int lanes_getrf_solve(double (&a)[(N + T - 1) / T][N],
                                                  double (&b)[(N + T - 1) / T],
                                                  int (&pos)[(N + T - 1) / T], int seg_base,
                                                  IpivSink ipiv_k, int tile = 0, double thresh = 0.0)
 {
-    return lanes_getrf_solve_x<N, T, kFMA, kTile, CH>(a, b, pos, seg_base, ipiv_k,
+    return lanes_getrf_solve_x<N, T, kFMA, kTile, CH, false, kSettle>(a, b, pos, seg_base, ipiv_k,
                                                       [](int, double) {}, tile, thresh);
 }
 

@@ -75,11 +75,15 @@ __global__ void __launch_bounds__(256) k_lanes(SolveArgs a, int layout, int fact
     constexpr int KP = (N + T - 1) / T;
     int pv[KP];
     static_for<0, KP>([&](auto sc) __attribute__((always_inline)) { pv[decltype(sc)::value] = 0; });
-    const int inf = lanes_getrf_solve<N, T, F, Tl>(m, x, pos, g * T, [&](int k, int v) {
+    constexpr bool kSettle = lanes_settle<N, T>();
+    const int inf = lanes_getrf_solve<N, T, F, Tl, 8, kSettle>(m, x, pos, g * T, [&](int k, int v) {
         const int c = k / T;
         static_for<0, KP>([&](auto sc) __attribute__((always_inline)) {
             constexpr int cc = decltype(sc)::value;
-            if (cc == c) pv[cc] = (t == k % T) ? v : pv[cc];
+            if (cc == c) {
+                pv[cc] = (t == k % T) ? v : pv[cc];
+                if constexpr (kSettle) settle(pv[cc]);
+            }
         });
     }, a.tile, a.thresh);
 

@@ -50,13 +50,15 @@ struct soa_shape {
     static constexpr int CJ0 = (4096 * WPB) / (NP * S * 8);
     static constexpr int CJ = CJ0 < 1 ? 1 : (CJ0 > N ? N : CJ0);
     static constexpr int NCH = (N + CJ - 1) / CJ;        /* chunks */
-    /* 512-thread workgroups (T = 32) need two per CU: at most 128 VGPRs */
-    static constexpr int MIN_WAVES_EU = WPB >= 8 ? 4 : 1;
-    /* pivot-row broadcast chunk: 16 columns where the kernel runs 2 waves
-     * per SIMD anyway (n >= 26 with 16 lanes; measured n = 32: 6.8 vs
-     * 7.1 ms), 8 below, where 16 would cost a wave per SIMD (n = 24: 4.4 vs
-     * 3.6 ms) */
-    static constexpr int CH = (T == 16 && N >= 26) ? 16 : 8;
+    /* 512-thread workgroups (T = 32) need two per CU: at most 128 VGPRs;
+     * 16 lanes (two rows per lane up to n = 32) fit 168 VGPRs, three waves
+     * per SIMD */
+    static constexpr int MIN_WAVES_EU = WPB >= 8 ? 4 : (T == 16 ? 3 : 1);
+    /* pivot-row broadcast chunk (columns) */
+    static constexpr int CH = 8;
+    /* global loads in flight during the staging: this many column chunks
+     * ahead of the one being transposed */
+    static constexpr int LA = 2;
     static_assert(NT == S * T, "shape");
 };
 
@@ -79,19 +81,26 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
     __shared__ int ipl[NP * S];
     __shared__ int infl[S];
 
-    const int tid = (int)threadIdx.x;
-    const int lane = (int)__lane_id();
-    const int g = lane / T, t = lane % T;
+    int tid = (int)threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t sys0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * S;
     const int64_t rem = a.batch - sys0;
     const int nvalid = (int)(rem < S ? rem : S);
 
-    /* cooperative side: system yw, rows ci0 + multiples of T */
-    const int yw = tid & (S - 1);
-    const int ci0 = tid >> Sh::LOG_S;
-    /* lane side: system yl, rows t + s*T */
-    const int yl = wave * Sh::SPW + g;
+    /* Lane geometry, all derived from tid (rebuilt after the solve from a
+     * fenced copy of tid, so that none of it stays live across the solve):
+     * lane side: segment g, lane t of the segment, system yl, rows t + s*T;
+     * cooperative side: system yw, rows ci0 + multiples of T. */
+    int g, t, yl, yw, ci0;
+    auto set_geometry = [&]() __attribute__((always_inline)) {
+        const int lane = tid & 63;
+        g = lane / T;
+        t = lane % T;
+        yl = wave * Sh::SPW + g;
+        yw = tid & (S - 1);
+        ci0 = tid >> Sh::LOG_S;
+    };
+    set_geometry();
 
     /* The cooperative rows of a wave are ci0 = cw .. cw + 64/S - 1, so each
      * descriptor is based at the wave's first row (a uniform address) and
@@ -104,8 +113,10 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
     constexpr int RW = 64 / S; /* cooperative rows per wave */
     const uint32_t bytesA = (uint32_t)(((int64_t)(RW - 1) * a.sA + nvalid) * 8);
     const uint32_t bytesB = (uint32_t)(((int64_t)(RW - 1) * a.sB + nvalid) * 8);
-    const uint32_t vA = yw < nvalid ? (uint32_t)(((int64_t)(ci0 - cw) * a.sA + yw) * 8) : kOutOfRange;
-    const uint32_t vB = yw < nvalid ? (uint32_t)(((int64_t)(ci0 - cw) * a.sB + yw) * 8) : kOutOfRange;
+    auto coop_off = [&](int64_t ld, int w) __attribute__((always_inline)) {
+        return yw < nvalid ? (uint32_t)(((int64_t)(ci0 - cw) * ld + yw) * w) : kOutOfRange;
+    };
+    uint32_t vA = coop_off(a.sA, 8), vB = coop_off(a.sB, 8);
     /* per-lane offset of the cooperative row ci0 + ib (out of range for rows past n) */
     auto rowv = [&](uint32_t v, int ib) -> uint32_t {
         return (ib + T <= N || ci0 < N - ib) ? v : kOutOfRange;
@@ -123,17 +134,26 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
         constexpr int s = decltype(sc)::value;
         pos[s] = t + s * T < N ? t + s * T : -1;
     });
-    /* every global load is issued up front (as many in flight as the
-     * direct-load kernel); the transposition then goes chunk by chunk, and
-     * the staging registers of a chunk die as its matrix registers fill */
+    /* the loads of column chunk c + LA are issued before chunk c is
+     * transposed, so LA + 1 chunks are in flight per wave while the staging
+     * registers of a chunk die as its matrix registers fill (the whole
+     * matrix in flight would hold 2*n*n/T extra VGPRs: a wave per SIMD) */
     double v[N * QB];
     double vb[QB];
-    static_for<0, N * QB>(LUPP_SF(qc) {
-        constexpr int q = decltype(qc)::value;
-        constexpr int j = q / QB, ib = (q % QB) * T;
-        const auto rc = make_rsrc(baseA + (int64_t)j * colA + (int64_t)ib * a.sA, bytesA);
-        v[q] = buf_load_f64(rc, rowv(vA, ib), 0);
-    });
+    auto load_chunk = [&](auto chc) __attribute__((always_inline)) {
+        constexpr int ch = decltype(chc)::value;
+        if constexpr (ch < NCH) {
+            constexpr int j0 = ch * CJ;
+            constexpr int cj = (j0 + CJ <= N) ? CJ : N - j0;
+            static_for<j0 * QB, (j0 + cj) * QB>(LUPP_SF(qc) {
+                constexpr int q = decltype(qc)::value;
+                constexpr int j = q / QB, ib = (q % QB) * T;
+                const auto rc = make_rsrc(baseA + (int64_t)j * colA + (int64_t)ib * a.sA, bytesA);
+                v[q] = buf_load_f64(rc, rowv(vA, ib), 0);
+            });
+        }
+    };
+    static_for<0, Sh::LA>(load_chunk);
     {
         static_for<0, QB>(LUPP_SF(qc) {
             constexpr int ib = decltype(qc)::value * T;
@@ -143,6 +163,7 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
     }
     static_for<0, NCH>(LUPP_SF(chc) {
         constexpr int ch = decltype(chc)::value;
+        load_chunk(std::integral_constant<int, ch + Sh::LA>{});
         constexpr int j0 = ch * CJ;
         constexpr int cj = (j0 + CJ <= N) ? CJ : N - j0;
         static_for<0, cj * QB>(LUPP_SF(qc) {
@@ -176,11 +197,15 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
     constexpr int KP = (N + T - 1) / T;
     int pv[KP];
     static_for<0, KP>(LUPP_SF(sc) { pv[decltype(sc)::value] = 0; });
-    const int inf = lanes_getrf_solve<N, T, F, Tl, Sh::CH>(m, x, pos, g * T, [&](int k, int val) {
+    constexpr bool kSettle = lanes_settle<N, T>();
+    const int inf = lanes_getrf_solve<N, T, F, Tl, Sh::CH, kSettle>(m, x, pos, g * T, [&](int k, int val) {
         const int c = k / T;
         static_for<0, KP>(LUPP_SF(sc) {
             constexpr int cc = decltype(sc)::value;
-            if (cc == c) pv[cc] = (t == k % T) ? val : pv[cc];
+            if (cc == c) {
+                pv[cc] = (t == k % T) ? val : pv[cc];
+                if constexpr (kSettle) settle(pv[cc]);
+            }
         });
     }, a.tile, a.thresh);
 
@@ -188,6 +213,10 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
     baseA = opaque_ptr(baseA);
     baseB = opaque_ptr(baseB);
     const int64_t sAs = opaque_i64(a.sA), sBs = opaque_i64(a.sB);
+    settle(tid);
+    set_geometry();
+    vA = coop_off(sAs, 8);
+    vB = coop_off(sBs, 8);
     if (factors) {
         static_for<0, NCH>(LUPP_SF(chc) {
             constexpr int j0 = decltype(chc)::value * CJ;
@@ -227,7 +256,7 @@ __global__ void __launch_bounds__((soa_shape<N, T>::NT))
         const bool ok = infl[yw] == 0;
         int32_t *baseP = a.ipiv + sys0 + (int64_t)cw * sAs;
         const uint32_t bytesP = (uint32_t)(((int64_t)(RW - 1) * sAs + nvalid) * 4);
-        const uint32_t vP = yw < nvalid ? (uint32_t)(((int64_t)(ci0 - cw) * sAs + yw) * 4) : kOutOfRange;
+        const uint32_t vP = coop_off(sAs, 4);
         static_for<0, QB>(LUPP_SF(qc) {
             constexpr int ib = decltype(qc)::value * T;
             buf_store_f64(make_rsrc(baseB + (int64_t)ib * sBs, bytesB), ok ? rowv(vB, ib) : kOutOfRange,
