@@ -170,3 +170,31 @@ def test_autotune_ragged_picks_a_supported_count(L, ctx):
         assert L.lupp_autotune_ragged(ctx, n, batch, A, b, reps=0)[0] == -6
     finally:
         assert L.lupp_set_ragged_lanes(ctx, n, saved) == 0
+
+
+def test_calls_on_two_streams_share_the_workspace(L, ctx):
+    """Two calls on one context, on different streams, queued without a host
+    synchronisation: the second (smaller) call must wait on the device for
+    the first one's kernels before it rebuilds the shared plan and index
+    list, so both batches come out as the oracle's."""
+    dev = torch.device("cuda:0")
+    big = mixed_systems(120000, seed=41, kappa_max=None)
+    small = mixed_systems(3001, seed=42, kappa_max=None)
+    refs = [oracle.gesv_ragged(m["n"], m["offA"], m["offB"], m["A"], m["b"], threads=8)
+            for m in (big, small)]
+    bufs = []
+    for m in (big, small):
+        t = {k: torch.from_numpy(np.ascontiguousarray(m[k])).to(dev) for k in ("n", "offA", "offB", "A", "b")}
+        t["ipiv"] = torch.full((m["b"].size,), -9, dtype=torch.int32, device=dev)
+        t["info"] = torch.full((m["n"].size,), -7, dtype=torch.int32, device=dev)
+        bufs.append(t)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)]
+    for t, m, st in zip(bufs, (big, small), streams):
+        rc = L.lupp_batched_solve_ragged(ctx, m["n"].size, t["n"], t["offA"], t["offB"], t["A"], t["b"],
+                                         t["ipiv"], t["info"], 0, st)
+        assert rc == 0, L.lupp_error_string(rc)
+    torch.cuda.synchronize()
+    for t, ref in zip(bufs, refs):
+        same(ref, {"LU": t["A"].cpu().numpy(), "x": t["b"].cpu().numpy(), "ipiv": t["ipiv"].cpu().numpy(),
+                   "info": t["info"].cpu().numpy()})
