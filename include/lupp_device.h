@@ -92,14 +92,23 @@ __device__ __forceinline__ void settle(V &x)
     asm volatile("" : "+v"(x));
 }
 
-/* Whether the batched lanes kernels fence the solver's per-step results:
- * where the unfenced kernel needs more than 168 VGPRs (16 lanes per system
- * from n = 27) and the fence buys a third wave per SIMD. Elsewhere it would
- * only hold the scheduler back (n = 24 on 16 lanes: 3.06 -> 3.23 ms). */
+/* Whether the batched lanes kernels fence the solver's per-step results,
+ * and their pivot-row broadcast chunk: the fence is used where it buys a
+ * wave per SIMD and the wave pays - 16 lanes per system from n = 27
+ * (195 -> 168 VGPRs at n = 32: three waves) and n = 20..24 with 4-column
+ * chunks (<= 128 VGPRs: four waves instead of three; 4-7% faster at 2^19
+ * systems, while n = 17..19 lost 1-3%). Elsewhere it would only hold the
+ * scheduler back (n = 24 at three waves either way: 3.06 -> 3.23 ms). */
 template <int N, int T>
 constexpr bool lanes_settle()
 {
-    return T == 16 && N >= 27;
+    return T == 16 && (N >= 27 || (N >= 20 && N <= 24));
+}
+
+template <int N, int T>
+constexpr int lanes_chunk()
+{
+    return (T == 16 && N >= 20 && N <= 24) ? 4 : 8;
 }
 
 /* a - l*u: in strict mode one rounded multiply then one rounded subtract;

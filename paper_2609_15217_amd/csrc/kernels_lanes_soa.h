@@ -55,7 +55,7 @@ struct soa_shape {
      * per SIMD */
     static constexpr int MIN_WAVES_EU = WPB >= 8 ? 4 : (T == 16 ? 3 : 1);
     /* pivot-row broadcast chunk (columns) */
-    static constexpr int CH = 8;
+    static constexpr int CH = lanes_chunk<N, T>();
     /* global loads in flight during the staging: this many column chunks
      * ahead of the one being transposed */
     static constexpr int LA = 2;
