@@ -247,6 +247,11 @@ __device__ __forceinline__ int thread_getrf_solve(double (&a)[N][N], double (&b)
         ipiv[k] = p + 1;
         const bool zero = (pv == 0.0);
         info = (zero && info == 0) ? k + 1 : info;
+        /* solve-only calls on systems that spill into AGPRs (the 13 x 13
+         * Newton steps): fenced, see settle - 190 -> 146 AGPRs, no VGPR
+         * spill, 2991 -> 2891 us; at 7 x 7 it removes registers without
+         * adding a wave (641 vs 632 us) */
+        if constexpr (!kFactors && N >= 10) settle(info);
         /* kRecip: the reciprocal needs only the pivot value, so its latency
          * runs under the interchange below (a zero pivot gives an unused
          * infinity) */
