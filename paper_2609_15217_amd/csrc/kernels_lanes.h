@@ -76,7 +76,10 @@ __global__ void __launch_bounds__(256) k_lanes(SolveArgs a, int layout, int fact
     int pv[KP];
     static_for<0, KP>([&](auto sc) __attribute__((always_inline)) { pv[decltype(sc)::value] = 0; });
     constexpr bool kSettle = lanes_settle<N, T>();
-    const int inf = lanes_getrf_solve<N, T, F, Tl, lanes_chunk<N, T>(), kSettle>(m, x, pos, g * T, [&](int k, int v) {
+    /* the tile-local instances hold the second search's values too: 4-column
+     * chunks keep them at three waves per SIMD (n = 32: 170 -> 162 VGPRs) */
+    constexpr int CH = (Tl && kSettle) ? 4 : lanes_chunk<N, T>();
+    const int inf = lanes_getrf_solve<N, T, F, Tl, CH, kSettle>(m, x, pos, g * T, [&](int k, int v) {
         const int c = k / T;
         static_for<0, KP>([&](auto sc) __attribute__((always_inline)) {
             constexpr int cc = decltype(sc)::value;
